@@ -1,0 +1,208 @@
+/* qtt.h — C ABI of the MI355X QTT finite element hot path.
+ *
+ * The operations follow the paper's statement of the problem (Alg. 1 and
+ * Sec. 4 of "A Low-Rank QTT-based Finite Element Method for Elasticity
+ * Problems"): assemble the global stiffness matrix K and load vector f in
+ * Z-ordered QTT form, multiply a QTT matrix by a QTT vector core by core
+ * (strong Kronecker product), round a tensor train to a relative accuracy
+ * (left-to-right QR sweep, right-to-left truncated SVD sweep; the cited
+ * TT-rounding algorithm), and solve K u = f to a stated accuracy.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - A tensor train (qtt_tt) is D cores.  Core k of a vector has shape
+ *   (r_k, n_k, r_{k+1}); core k of a matrix (r_k, n_k, m_k, r_{k+1}).  Cores
+ *   are packed back to back in `data` in the order k = 0..D-1, each stored
+ *   column-major (the left rank index varies fastest, then n, then m, then
+ *   the right rank).  r_0 = r_D = 1.
+ * - The first core carries the least significant digit of the global index:
+ *   i = i_0 + n_0 (i_1 + n_1 (i_2 + ...)).  For the elasticity problem the
+ *   cores are [component | subdomain (q > 1 only) | i1 j1 i2 j2 ... id jd],
+ *   so the global dof index is c + 2 (m + q Z(i, j)) with Z the Z-order of
+ *   Sec. 3.2.
+ * - All values are FP64 in device memory.  `ranks`, `nrow`, `ncol` are host
+ *   arrays.  The caller owns every buffer; the library never allocates
+ *   device memory: each call takes a caller-provided device workspace
+ *   (`ws`, `ws_bytes`, 256-byte aligned) whose size the matching
+ *   *_workspace call reports.
+ * - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *   their kernels on it.  A call whose outputs include host-side ranks or
+ *   scalars synchronises that stream before returning; this is stated per
+ *   call.
+ * - Errors: every call returns a qtt_status; a negative value is an error
+ *   and qtt_last_error() returns a description (thread-local).  Nothing
+ *   throws across the ABI.  On error the outputs are unspecified.
+ */
+#ifndef QTT_H
+#define QTT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QTT_MAX_CORES 40
+
+typedef enum {
+  QTT_OK = 0,
+  QTT_E_INVAL = -1,       /* bad argument (NULL pointer, bad value)          */
+  QTT_E_SHAPE = -2,       /* modes or ranks of the operands do not agree     */
+  QTT_E_CAPACITY = -3,    /* an output buffer or the workspace is too small  */
+  QTT_E_NOCONV = -4,      /* the solve did not reach its tolerance           */
+  QTT_E_HIP = -5,         /* a HIP runtime call failed                       */
+  QTT_E_UNSUPPORTED = -7  /* valid request that this library does not do     */
+} qtt_status;
+
+typedef enum { QTT_F64 = 0, QTT_F32 = 1, QTT_BF16 = 2 } qtt_dtype;
+
+/* A tensor train in caller-owned memory.  `ncol == NULL` marks a vector. */
+typedef struct {
+  int32_t ncores;
+  const int32_t *nrow;   /* host, ncores mode sizes                         */
+  const int32_t *ncol;   /* host, ncores column mode sizes, or NULL         */
+  int32_t *ranks;        /* host, ncores + 1 ranks; inputs read them,
+                            producers write them                           */
+  double *data;          /* device, packed cores                            */
+  int64_t capacity;      /* number of doubles available at `data`           */
+} qtt_tt;
+
+/* ------------------------------------------------------------ problem
+ * One square subdomain [x0, x0+side] x [y0, y0+side] carrying 2^level nodes
+ * per side (Sec. 3.2).  fixed[s][c] != 0 clamps component c (0 = x, 1 = y)
+ * on side s (0 = west, 1 = east, 2 = south, 3 = north) (Sec. 3.6).        */
+typedef struct {
+  double x0, y0, side;
+  uint8_t fixed[4][2];
+} qtt_square;
+
+/* Traction t_comp(s) = sum_{k=1..nmodes} amp[k-1] sin(k pi s) on side
+ * `side` of subdomain `sub`, s in [0, 1] the normalised arclength.         */
+typedef struct {
+  int32_t sub, side, comp, nmodes;
+  const double *amp;
+} qtt_traction;
+
+typedef struct {
+  int32_t level;            /* d: 2^d nodes per subdomain side              */
+  int32_t q;                /* number of square subdomains (1..8)           */
+  const qtt_square *sub;    /* q squares of equal side, edge-to-edge        */
+  double E, nu;             /* Young's modulus and Poisson's ratio (Sec. 2) */
+  int32_t plane_strain;     /* 1 plane strain, 0 plane stress              */
+  double body[2];           /* constant body force                          */
+  int32_t ntrac;
+  const qtt_traction *trac;
+  int32_t coupling;         /* q > 1: 0 = symmetric exact coupling (copy
+                               averaging plus copy Laplacian), 1 = the
+                               paper's coupling rows (Sec. 3.5.1); the
+                               latter is not symmetric and is for assembly
+                               only                                        */
+} qtt_problem;
+
+/* qtt_assemble_stiffness — Alg. 1: global stiffness K and load f in
+ * Z-ordered QTT form after coupling and Dirichlet conditions.
+ *   K_bc = P K P + gamma_D (I - P), f_bc = P f, P = diag(mask),
+ *   gamma_D = trace(K)/N; q > 1 couples replicated interface nodes
+ *   (coupling field above) with gamma = mean diagonal of one subdomain's
+ *   stiffness.
+ * The stiffness uses exact 2x2 Gauss quadrature of the Q1 element integrals
+ * (Sec. 3.3-3.4), the loads are mass matrices times nodal intensities
+ * (eq. load:vector:intensity and its edge analogue).  Both results are
+ * rounded to relative accuracy `eps` (use 1e-14).
+ * K: matrix with ncores = 1 + (q>1) + 2 level, nrow = ncol = modes; f: vector
+ * with the same modes.  The caller provides nrow/ncol arrays and data
+ * buffers; ranks are written.  Synchronises `stream`.                      */
+qtt_status qtt_assemble_stiffness(const qtt_problem *prob, double eps,
+                                  qtt_tt *K, qtt_tt *f, void *ws,
+                                  size_t ws_bytes, void *stream);
+qtt_status qtt_assemble_workspace(const qtt_problem *prob, size_t *bytes,
+                                  int64_t *K_capacity, int64_t *f_capacity);
+
+/* qtt_matvec — y = A x core by core (strong Kronecker product, Sec. 4):
+ *   y_k[(a,b), i, (c,d)] = sum_j A_k[a, i, j, c] x_k[b, j, d],
+ * with the pair index (a,b) -> a r^x + b.  Output ranks are products of the
+ * input ranks and are written to y->ranks (host, no synchronisation).
+ * `compute`: QTT_F64, or QTT_F32 / QTT_BF16 to read the operands rounded to
+ * that type and accumulate in FP32 (the result is stored in FP64).         */
+qtt_status qtt_matvec(const qtt_tt *A, const qtt_tt *x, qtt_tt *y,
+                      qtt_dtype compute, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/* qtt_round — TT rounding in place (the cited rounding algorithm): a
+ * left-to-right Householder QR sweep moves the norm into the last core,
+ * then a right-to-left sweep of truncated SVDs keeps at each bond the
+ * smallest rank r with sqrt(sum_{i>=r} sigma_i^2) <= eps ||x|| / sqrt(D-1),
+ * capped at rmax (rmax <= 0: no cap).  Matrices are rounded with the long
+ * index (i, j) as one mode.  Writes the new ranks to x->ranks, the norm
+ * ||x||_F to *norm and sqrt(sum of all discarded sigma^2) to *err (either
+ * pointer may be NULL).  Synchronises `stream`.                            */
+qtt_status qtt_round(qtt_tt *x, double eps, int32_t rmax, double *norm,
+                     double *err, void *ws, size_t ws_bytes, void *stream);
+qtt_status qtt_round_workspace(const qtt_tt *x, int32_t rmax, size_t *bytes);
+
+/* qtt_dot — <x, y> of two TT vectors of equal modes (left-to-right
+ * environment sweep).  Synchronises `stream`.                              */
+qtt_status qtt_dot(const qtt_tt *x, const qtt_tt *y, double *out, void *ws,
+                   size_t ws_bytes, void *stream);
+
+/* qtt_axpby — z = a x + b y by core concatenation (ranks add): the first
+ * cores sit side by side, middle cores block-diagonally, last cores stacked;
+ * a and b scale the first core.  z must not alias x or y.  Writes z->ranks
+ * (host, no synchronisation); the workspace needs 1 KiB.                   */
+qtt_status qtt_axpby(double a, const qtt_tt *x, double b, const qtt_tt *y,
+                     qtt_tt *z, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------ solve   */
+typedef struct {
+  double tol;        /* stop when ||f - K u|| <= tol ||f|| (FP64)            */
+  double eps;        /* rounding accuracy of the iterate u                    */
+  int32_t rmax;      /* rank cap of u                                         */
+  double eps_in;     /* rounding accuracy inside the correction solve         */
+  int32_t rmax_in;   /* rank cap inside the correction solve                  */
+  double red_in;     /* relative residual reduction of each correction solve  */
+  int32_t maxit_in;  /* CG iterations per correction solve                   */
+  int32_t maxit_out; /* refinement steps                                      */
+  int32_t check_every; /* CG iterations between host convergence checks      */
+  qtt_dtype compute; /* contractions: QTT_F64, QTT_F32 or QTT_BF16 (QR, SVD,
+                        dot products and the outer residual stay FP64)       */
+  int32_t sketch;    /* 0: exact rounding of every product K p; > 0: round
+                        products by a randomised sketch of this oversampling
+                        before the exact rounding                            */
+  uint64_t seed;     /* seed of the sketch generator (Philox4x32-10)         */
+} qtt_solve_opts;
+
+typedef struct {
+  int32_t status;         /* QTT_OK or QTT_E_NOCONV                           */
+  int32_t outer;          /* refinement steps taken                           */
+  int32_t inner;          /* CG iterations in total                           */
+  double residual;        /* final ||f - K u|| / ||f|| in FP64                */
+  double residual_hist[64]; /* residual before each refinement step         */
+  int32_t max_rank;       /* largest bond rank of u                           */
+} qtt_solve_report;
+
+/* qtt_solve — solve K u = f (K symmetric positive definite) by conjugate
+ * gradients on the QTT format with FP64 iterative refinement: the outer
+ * loop forms the residual f - K u exactly (product, difference) and rounds
+ * it, the inner loop runs CG on K e = r with every iterate rounded to
+ * (eps_in, rmax_in), and u <- round(u + e, eps, rmax).  x0 (NULL: zero) is
+ * the starting guess.  u must have capacity for rank rmax.  Writes u->ranks
+ * and the report.  Synchronises `stream`.  Returns QTT_E_NOCONV (with the
+ * last iterate in u) when maxit_out is reached.                            */
+qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
+                     const qtt_solve_opts *opts, qtt_tt *u,
+                     qtt_solve_report *report, void *ws, size_t ws_bytes,
+                     void *stream);
+qtt_status qtt_solve_workspace(const qtt_tt *K, const qtt_tt *f,
+                               const qtt_solve_opts *opts, size_t *bytes);
+
+/* Thread-local text of the last error of this thread.                      */
+const char *qtt_last_error(void);
+
+/* Library version string.                                                  */
+const char *qtt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QTT_H */

@@ -1,0 +1,348 @@
+"""ctypes binding of libqtt.so (see include/qtt.h for the contract)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqtt.so")
+
+QTT_F64, QTT_F32, QTT_BF16 = 0, 1, 2
+_DTYPES = {"f64": QTT_F64, "f32": QTT_F32, "bf16": QTT_BF16}
+MAX_CORES = 40
+
+
+class QttError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("qtt status %d: %s" % (status, msg))
+        self.status = status
+
+
+class _TT(C.Structure):
+    _fields_ = [("ncores", C.c_int32), ("nrow", C.POINTER(C.c_int32)),
+                ("ncol", C.POINTER(C.c_int32)), ("ranks", C.POINTER(C.c_int32)),
+                ("data", C.c_void_p), ("capacity", C.c_int64)]
+
+
+class _Square(C.Structure):
+    _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("side", C.c_double),
+                ("fixed", (C.c_uint8 * 2) * 4)]
+
+
+class _Traction(C.Structure):
+    _fields_ = [("sub", C.c_int32), ("side", C.c_int32), ("comp", C.c_int32),
+                ("nmodes", C.c_int32), ("amp", C.POINTER(C.c_double))]
+
+
+class _Problem(C.Structure):
+    _fields_ = [("level", C.c_int32), ("q", C.c_int32), ("sub", C.POINTER(_Square)),
+                ("E", C.c_double), ("nu", C.c_double), ("plane_strain", C.c_int32),
+                ("body", C.c_double * 2), ("ntrac", C.c_int32),
+                ("trac", C.POINTER(_Traction)), ("coupling", C.c_int32)]
+
+
+class _SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("eps", C.c_double), ("rmax", C.c_int32),
+                ("eps_in", C.c_double), ("rmax_in", C.c_int32), ("red_in", C.c_double),
+                ("maxit_in", C.c_int32), ("maxit_out", C.c_int32),
+                ("check_every", C.c_int32), ("compute", C.c_int32),
+                ("sketch", C.c_int32), ("seed", C.c_uint64)]
+
+
+class _SolveReport(C.Structure):
+    _fields_ = [("status", C.c_int32), ("outer", C.c_int32), ("inner", C.c_int32),
+                ("residual", C.c_double), ("residual_hist", C.c_double * 64),
+                ("max_rank", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libqtt.so; raises if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libqtt.so not built: run `python -m paper_2501_07778_amd.build` "
+                          "(expected at %s)" % path)
+    L = C.CDLL(path)
+    P = C.POINTER
+    vp, sz = C.c_void_p, C.c_size_t
+    L.qtt_last_error.restype = C.c_char_p
+    L.qtt_version.restype = C.c_char_p
+    L.qtt_matvec.argtypes = [P(_TT), P(_TT), P(_TT), C.c_int, vp, sz, vp]
+    L.qtt_round.argtypes = [P(_TT), C.c_double, C.c_int32, P(C.c_double), P(C.c_double),
+                            vp, sz, vp]
+    L.qtt_round_workspace.argtypes = [P(_TT), C.c_int32, P(sz)]
+    L.qtt_dot.argtypes = [P(_TT), P(_TT), P(C.c_double), vp, sz, vp]
+    L.qtt_axpby.argtypes = [C.c_double, P(_TT), C.c_double, P(_TT), P(_TT), vp, sz, vp]
+    L.qtt_assemble_stiffness.argtypes = [P(_Problem), C.c_double, P(_TT), P(_TT), vp, sz, vp]
+    L.qtt_assemble_workspace.argtypes = [P(_Problem), P(sz), P(C.c_int64), P(C.c_int64)]
+    L.qtt_solve.argtypes = [P(_TT), P(_TT), P(_TT), P(_SolveOpts), P(_TT), P(_SolveReport),
+                            vp, sz, vp]
+    L.qtt_solve_workspace.argtypes = [P(_TT), P(_TT), P(_SolveOpts), P(sz)]
+    for name in ("qtt_matvec", "qtt_round", "qtt_round_workspace", "qtt_dot", "qtt_axpby",
+                 "qtt_assemble_stiffness", "qtt_assemble_workspace", "qtt_solve",
+                 "qtt_solve_workspace"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def lib():
+    return load_library()
+
+
+def version() -> str:
+    return lib().qtt_version().decode()
+
+
+def _check(st: int):
+    if st != 0:
+        raise QttError(st, lib().qtt_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _workspace(nbytes: int):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device="cuda")
+
+
+def _aligned_ptr(buf) -> int:
+    p = buf.data_ptr()
+    return (p + 255) & ~255
+
+
+# ---------------------------------------------------------------- TT handle
+class TT:
+    """A tensor train in a torch float64 device buffer (packed column-major
+    cores, see include/qtt.h)."""
+
+    def __init__(self, nrow: Sequence[int], ncol: Optional[Sequence[int]],
+                 ranks: Sequence[int], capacity: int, data=None):
+        torch = _torch()
+        self.D = len(nrow)
+        self._nrow = (C.c_int32 * self.D)(*nrow)
+        self._ncol = (C.c_int32 * self.D)(*ncol) if ncol is not None else None
+        self._ranks = (C.c_int32 * (self.D + 1))(*ranks)
+        self.capacity = int(capacity)
+        self.data = data if data is not None else torch.zeros(
+            max(self.capacity, 1), dtype=torch.float64, device="cuda")
+        self.c = _TT(self.D, self._nrow,
+                     C.cast(self._ncol, C.POINTER(C.c_int32)) if self._ncol is not None else None,
+                     self._ranks, self.data.data_ptr(), self.capacity)
+
+    @property
+    def nrow(self) -> List[int]:
+        return list(self._nrow)
+
+    @property
+    def ncol(self) -> Optional[List[int]]:
+        return list(self._ncol) if self._ncol is not None else None
+
+    @property
+    def ranks(self) -> List[int]:
+        return list(self._ranks)
+
+    def set_ranks(self, r: Sequence[int]):
+        for k, v in enumerate(r):
+            self._ranks[k] = int(v)
+
+    def numel(self) -> int:
+        r, n = self.ranks, self.nrow
+        m = self.ncol or [1] * self.D
+        return sum(r[k] * n[k] * m[k] * r[k + 1] for k in range(self.D))
+
+    @classmethod
+    def empty(cls, nrow, ncol, capacity):
+        return cls(nrow, ncol, [1] * (len(nrow) + 1), capacity)
+
+
+def tt_from_cores(cores: Sequence[np.ndarray], capacity: Optional[int] = None) -> TT:
+    """Upload NumPy cores ((r0,n,r1) vectors or (r0,n,m,r1) matrices) into the
+    packed column-major device layout."""
+    torch = _torch()
+    mat = cores[0].ndim == 4
+    nrow = [c.shape[1] for c in cores]
+    ncol = [c.shape[2] for c in cores] if mat else None
+    ranks = [cores[0].shape[0]] + [c.shape[-1] for c in cores]
+    flat = np.concatenate([np.reshape(np.asarray(c, dtype=np.float64), -1, order="F")
+                           for c in cores])
+    cap = int(capacity) if capacity is not None else flat.size
+    data = torch.zeros(max(cap, 1), dtype=torch.float64, device="cuda")
+    data[:flat.size] = torch.from_numpy(flat).to("cuda")
+    return TT(nrow, ncol, ranks, cap, data)
+
+
+def tt_to_cores(t: TT) -> List[np.ndarray]:
+    """Download a TT into NumPy cores (same shapes as the oracle uses)."""
+    flat = t.data[:t.numel()].cpu().numpy()
+    r, n = t.ranks, t.nrow
+    m = t.ncol
+    out, o = [], 0
+    for k in range(t.D):
+        shape = (r[k], n[k], m[k], r[k + 1]) if m is not None else (r[k], n[k], r[k + 1])
+        size = int(np.prod(shape))
+        out.append(np.reshape(flat[o:o + size], shape, order="F"))
+        o += size
+    return out
+
+
+# ---------------------------------------------------------------- ops
+def matvec(A: TT, x: TT, compute: str = "f64", y: Optional[TT] = None) -> TT:
+    """y = A x (strong Kronecker product of cores); output ranks multiply."""
+    ranks = [a * b for a, b in zip(A.ranks, x.ranks)]
+    need = sum(ranks[k] * A.nrow[k] * ranks[k + 1] for k in range(A.D))
+    if y is None:
+        y = TT(A.nrow, None, [1] * (A.D + 1), need)
+    ws = _workspace(4096)
+    _check(lib().qtt_matvec(C.byref(A.c), C.byref(x.c), C.byref(y.c), _DTYPES[compute],
+                            C.c_void_p(_aligned_ptr(ws)), ws.numel() - 256, _stream_ptr()))
+    y._keep = ws
+    return y
+
+
+def round_(x: TT, eps: float, rmax: int = 0):
+    """TT rounding in place; returns (norm, discarded-sigma bound)."""
+    need = C.c_size_t()
+    _check(lib().qtt_round_workspace(C.byref(x.c), int(rmax), C.byref(need)))
+    ws = _workspace(need.value)
+    nrm, err = C.c_double(), C.c_double()
+    _check(lib().qtt_round(C.byref(x.c), float(eps), int(rmax), C.byref(nrm), C.byref(err),
+                           C.c_void_p(_aligned_ptr(ws)), ws.numel() - 256, _stream_ptr()))
+    return nrm.value, err.value
+
+
+def dot(x: TT, y: TT) -> float:
+    caps = max(max(x.ranks) * max(y.ranks) * 3 * max(x.nrow), 1024)
+    ws = _workspace(8 * caps + 8192)
+    out = C.c_double()
+    _check(lib().qtt_dot(C.byref(x.c), C.byref(y.c), C.byref(out),
+                         C.c_void_p(_aligned_ptr(ws)), ws.numel() - 256, _stream_ptr()))
+    return out.value
+
+
+def axpby(a: float, x: TT, b: float, y: TT) -> TT:
+    ranks = [1] + [x.ranks[k] + y.ranks[k] for k in range(1, x.D)] + [1]
+    m = x.ncol or [1] * x.D
+    need = sum(ranks[k] * x.nrow[k] * m[k] * ranks[k + 1] for k in range(x.D))
+    z = TT(x.nrow, x.ncol, [1] * (x.D + 1), need)
+    ws = _workspace(4096)
+    _check(lib().qtt_axpby(float(a), C.byref(x.c), float(b), C.byref(y.c), C.byref(z.c),
+                           C.c_void_p(_aligned_ptr(ws)), ws.numel() - 256, _stream_ptr()))
+    z._keep = ws
+    return z
+
+
+# ---------------------------------------------------------------- problem
+@dataclass
+class Problem:
+    """Owner of the ctypes structures describing one elasticity problem."""
+    c: _Problem
+    keep: list
+
+
+def problem_from_workload(p, coupling: str = "symmetric") -> Problem:
+    """Marshal a workload description (attributes level, subs, E, nu,
+    plane_strain, body, tractions) into the C structure."""
+    subs = (_Square * len(p.subs))()
+    for i, s in enumerate(p.subs):
+        subs[i].x0, subs[i].y0, subs[i].side = s.x0, s.y0, s.side
+        for a in range(4):
+            for b in range(2):
+                subs[i].fixed[a][b] = 1 if s.fixed[a][b] else 0
+    keep = [subs]
+    trs = (_Traction * max(len(p.tractions), 1))()
+    for i, t in enumerate(p.tractions):
+        amp = (C.c_double * len(t.amp))(*t.amp)
+        keep.append(amp)
+        trs[i].sub, trs[i].side, trs[i].comp, trs[i].nmodes = t.sub, t.side, t.comp, len(t.amp)
+        trs[i].amp = amp
+    keep.append(trs)
+    c = _Problem(p.level, len(p.subs), subs, p.E, p.nu, 1 if p.plane_strain else 0,
+                 (C.c_double * 2)(*p.body), len(p.tractions), trs,
+                 1 if coupling == "paper" else 0)
+    return Problem(c, keep)
+
+
+def qtt_modes(level: int, q: int) -> List[int]:
+    return [2] + ([q] if q > 1 else []) + [2] * (2 * level)
+
+
+def assemble(p, coupling: str = "symmetric", eps: float = 1e-14):
+    """qtt_assemble_stiffness: returns (K, f) as device TTs."""
+    prob = problem_from_workload(p, coupling)
+    wsb, kc, fc = C.c_size_t(), C.c_int64(), C.c_int64()
+    _check(lib().qtt_assemble_workspace(C.byref(prob.c), C.byref(wsb), C.byref(kc), C.byref(fc)))
+    modes = qtt_modes(p.level, len(p.subs))
+    K = TT(modes, modes, [1] * (len(modes) + 1), kc.value)
+    f = TT(modes, None, [1] * (len(modes) + 1), fc.value)
+    ws = _workspace(wsb.value)
+    _check(lib().qtt_assemble_stiffness(C.byref(prob.c), float(eps), C.byref(K.c), C.byref(f.c),
+                                        C.c_void_p(_aligned_ptr(ws)), ws.numel() - 256,
+                                        _stream_ptr()))
+    return K, f
+
+
+# ---------------------------------------------------------------- solve
+@dataclass
+class SolveOpts:
+    tol: float = 1e-10
+    eps: float = 1e-10
+    rmax: int = 64
+    eps_in: float = 1e-3
+    rmax_in: int = 32
+    red_in: float = 1e-2
+    maxit_in: int = 2000
+    maxit_out: int = 40
+    check_every: int = 10
+    compute: str = "f64"
+    sketch: int = 0
+    seed: int = 0
+
+    def c(self) -> _SolveOpts:
+        return _SolveOpts(self.tol, self.eps, self.rmax, self.eps_in, self.rmax_in,
+                          self.red_in, self.maxit_in, self.maxit_out, self.check_every,
+                          _DTYPES[self.compute], self.sketch, self.seed)
+
+
+def solve_workspace_bytes(K: TT, f: TT, opts: SolveOpts) -> int:
+    o = opts.c()
+    n = C.c_size_t()
+    _check(lib().qtt_solve_workspace(C.byref(K.c), C.byref(f.c), C.byref(o), C.byref(n)))
+    return n.value
+
+
+def solve(K: TT, f: TT, opts: SolveOpts, x0: Optional[TT] = None, ws=None):
+    """qtt_solve; returns (u, report dict)."""
+    o = opts.c()
+    D = K.D
+    u_cap = sum(min(opts.rmax, 2 ** 30) ** 2 * K.nrow[k] for k in range(D))
+    u = TT(K.nrow, None, [1] * (D + 1), u_cap)
+    if ws is None:
+        ws = _workspace(solve_workspace_bytes(K, f, opts))
+    rep = _SolveReport()
+    st = lib().qtt_solve(C.byref(K.c), C.byref(f.c), C.byref(x0.c) if x0 is not None else None,
+                         C.byref(o), C.byref(u.c), C.byref(rep),
+                         C.c_void_p(_aligned_ptr(ws)), ws.numel() - 256, _stream_ptr())
+    if st not in (0, -4):
+        _check(st)
+    report = dict(status=rep.status, outer=rep.outer, inner=rep.inner,
+                  residual=rep.residual,
+                  residual_hist=[rep.residual_hist[i] for i in range(min(rep.outer + 1, 64))],
+                  max_rank=rep.max_rank)
+    return u, report

@@ -1,0 +1,135 @@
+// internal.h — shared declarations of the QTT library (host and device).
+//
+// Internal tensor trains are "slotted": core k lives at a fixed element
+// offset computed on the host from rank caps, and the actual ranks live in
+// device memory.  Kernels read the ranks and exit early on work beyond them,
+// so sequences of kernels (a rounding sweep, a CG iteration) run without
+// host round trips.  Cores are column-major: element (a, i, j, b) of a
+// matrix core with ranks (r0, r1) and modes (n, m) sits at
+// a + r0 * (i + n * (j + m * b)); vectors have m = 1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/qtt.h"
+
+#define QTT_MAXD QTT_MAX_CORES
+
+namespace qtt {
+
+struct TTView {
+  int32_t D;
+  int32_t n[QTT_MAXD];      // row modes
+  int32_t m[QTT_MAXD];      // column modes (1 for vectors)
+  int64_t off[QTT_MAXD];    // element offset of slot k in `data`
+  int32_t cap[QTT_MAXD + 1];  // rank caps the slots are sized for
+  int32_t *rk;              // device ranks (D + 1 entries)
+  double *data;
+};
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+qtt_status fail(qtt_status st, const std::string &msg);
+#define QTT_HIP(call)                                                     \
+  do {                                                                    \
+    hipError_t e_ = (call);                                               \
+    if (e_ != hipSuccess)                                                 \
+      return ::qtt::fail(QTT_E_HIP, std::string(#call) + ": " +           \
+                                        hipGetErrorString(e_));           \
+  } while (0)
+
+// ---------------------------------------------------------------- arena
+// Bump allocator over the caller's workspace; `dry` mode only counts.
+struct Arena {
+  char *base = nullptr;
+  size_t size = 0;
+  size_t used = 0;
+  bool dry = false;
+  void *take(size_t bytes) {
+    size_t a = (used + 255) & ~size_t(255);
+    used = a + ((bytes + 255) & ~size_t(255));
+    if (dry || used > size) return nullptr;
+    return base + a;
+  }
+  bool ok() const { return dry || used <= size; }
+};
+
+// slotted TT bookkeeping on the host
+struct TTDesc {
+  TTView v;          // passed by value to kernels
+  int64_t elems = 0; // total slot elements
+  int rmax_cap() const {
+    int r = 1;
+    for (int k = 0; k <= v.D; ++k) r = r > v.cap[k] ? r : v.cap[k];
+    return r;
+  }
+};
+
+// Fill modes and caps, compute slot offsets; returns total elements.
+int64_t layout(TTView &v, int D, const int32_t *n, const int32_t *m,
+               const std::vector<int> &caps);
+// caps for a TT of uniform cap r limited by the mode products from each end
+std::vector<int> bounded_caps(int D, const int32_t *n, const int32_t *m,
+                              int r);
+// allocate a slotted TT (data + device ranks) from the arena
+bool arena_tt(Arena &ar, TTDesc &t, int D, const int32_t *n,
+              const int32_t *m, const std::vector<int> &caps);
+
+// ---------------------------------------------------------------- kernels
+// All launchers enqueue on `s` and return hipGetLastError().
+hipError_t launch_matvec(const TTView &A, const TTView &x, const TTView &y,
+                         qtt_dtype compute, hipStream_t s);
+hipError_t launch_set_product_ranks(const TTView &A, const TTView &x,
+                                    const TTView &y, hipStream_t s);
+
+// packed <-> slotted copies; `ranks_dev` of the packed side are the
+// slotted side's device ranks.
+hipError_t launch_unpack(const double *packed, const TTView &dst,
+                         hipStream_t s);
+hipError_t launch_pack(const TTView &src, double *packed, hipStream_t s);
+hipError_t launch_copy_tt(const TTView &src, const TTView &dst,
+                          hipStream_t s);
+
+// z = a*x + b*y by core concatenation.  a_dev/b_dev (may be NULL) multiply
+// the host scalars.
+hipError_t launch_axpby(double a, const double *a_dev, const TTView &x,
+                        double b, const double *b_dev, const TTView &y,
+                        const TTView &z, hipStream_t s);
+// <x, y> into *out (device), workspace of `ws_elems` doubles
+hipError_t launch_dot(const TTView &x, const TTView &y, double *out,
+                      double *ws, int64_t ws_elems, hipStream_t s);
+int64_t dot_ws_elems(const TTView &x, const TTView &y);
+// tiny scalar programs on device scalars
+hipError_t launch_scalar(int op, double *s0, const double *s1,
+                         const double *s2, double c, hipStream_t s);
+enum ScalarOp {
+  SC_DIV = 0,        // s0 = s1 / s2
+  SC_NEG = 1,        // s0 = -s1
+  SC_COPY = 2,       // s0 = s1
+  SC_SQRT_DIV = 3,   // s0 = sqrt(max(s1,0)) / c
+  SC_SET = 4         // s0 = c
+};
+
+// rounding (exact algorithm); ws sized by round_workspace_elems
+struct RoundWs {
+  double *carry, *rbuf, *work, *vbuf, *fold, *scal;  // scal: norm, err2
+  int *iwork;
+  int64_t carry_elems, sq_elems;
+};
+int64_t round_ws_bytes(const TTView &x);
+bool round_ws_take(Arena &ar, const TTView &x, RoundWs &w);
+// rounds x in place: ranks stay on the device; norm -> w.scal[0],
+// sum of discarded sigma^2 -> w.scal[1].  eps_dev (may be NULL) replaces
+// eps by *eps_dev (device scalar).
+hipError_t round_tt(const TTView &x, double eps, int rmax, const RoundWs &w,
+                    hipStream_t s);
+
+// fills the device ranks from a host array
+hipError_t upload_ranks(const TTView &v, const int32_t *ranks,
+                        hipStream_t s);
+
+}  // namespace qtt

@@ -1,0 +1,383 @@
+// k_tt.hip — QTT matrix-vector product and the tensor-train glue used by
+// the solver (sums, inner products, packing), gfx950.
+//
+// The matrix-vector product is the strong Kronecker product of cores
+// (Sec. 4): y_k[(a,b), i, (c,d)] = sum_j A_k[a,i,j,c] x_k[b,j,d].  It reads
+// two small operand cores and writes an output core that is R*r times larger
+// in each rank, so it is bound by HBM writes: the kernel streams the output
+// once, fully coalesced along the fastest index b (the rank of x), with the
+// operand values kept in registers.
+#include <hip/hip_bf16.h>
+
+#include "internal.h"
+
+namespace qtt {
+
+namespace {
+
+constexpr int MV_TX = 64;   // lanes along b (output rows of one column)
+constexpr int MV_TY = 4;    // waves along a
+constexpr int MV_MMAX = 8;  // largest column mode handled
+
+template <typename T>
+__device__ __forceinline__ float to_compute(double v);
+template <>
+__device__ __forceinline__ float to_compute<float>(double v) {
+  return static_cast<float>(v);
+}
+template <>
+__device__ __forceinline__ float to_compute<__hip_bfloat16>(double v) {
+  return __bfloat162float(__float2bfloat16(static_cast<float>(v)));
+}
+
+// One block per output column (i, c, d) of core blockIdx.y; the P = ra0*rx0
+// rows of the column are contiguous in memory.
+__global__ void __launch_bounds__(MV_TX *MV_TY)
+    k_matvec_f64(TTView A, TTView x, TTView y) {
+  const int k = blockIdx.y;
+  const int ra0 = A.rk[k], ra1 = A.rk[k + 1];
+  const int rx0 = x.rk[k], rx1 = x.rk[k + 1];
+  if (blockIdx.x == 0 && k == 0 && threadIdx.x <= A.D)
+    y.rk[threadIdx.x] = A.rk[threadIdx.x] * x.rk[threadIdx.x];
+  const int n = A.n[k], m = A.m[k];
+  const int P = ra0 * rx0;
+  const int ncols = n * ra1 * rx1;
+  const double *Ak = A.data + A.off[k];
+  const double *xk = x.data + x.off[k];
+  double *yk = y.data + y.off[k];
+  const int tx = threadIdx.x % MV_TX, ty = threadIdx.x / MV_TX;
+  for (int col = blockIdx.x; col < ncols; col += gridDim.x) {
+    const int i = col % n;
+    const int s = col / n;
+    const int c = s / rx1;
+    const int d = s - c * rx1;
+    double *ycol = yk + (int64_t)P * col;
+    for (int b0 = 0; b0 < rx0; b0 += MV_TX) {
+      const int b = b0 + tx;
+      const bool act = b < rx0;
+      double xv[MV_MMAX];
+#pragma unroll
+      for (int j = 0; j < MV_MMAX; ++j)
+        xv[j] = (act && j < m) ? xk[b + (int64_t)rx0 * (j + m * d)] : 0.0;
+      for (int a = ty; a < ra0; a += MV_TY) {
+        const double *Aa = Ak + a + (int64_t)ra0 * (i + (int64_t)n * m * c);
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < MV_MMAX; ++j)
+          if (j < m) acc = fma(Aa[(int64_t)ra0 * n * j], xv[j], acc);
+        if (act) ycol[a * rx0 + b] = acc;
+      }
+    }
+  }
+}
+
+// Mixed precision: operands rounded to T, products accumulated in FP32.
+template <typename T>
+__global__ void __launch_bounds__(MV_TX *MV_TY)
+    k_matvec_lp(TTView A, TTView x, TTView y) {
+  const int k = blockIdx.y;
+  const int ra0 = A.rk[k], ra1 = A.rk[k + 1];
+  const int rx0 = x.rk[k], rx1 = x.rk[k + 1];
+  if (blockIdx.x == 0 && k == 0 && threadIdx.x <= A.D)
+    y.rk[threadIdx.x] = A.rk[threadIdx.x] * x.rk[threadIdx.x];
+  const int n = A.n[k], m = A.m[k];
+  const int P = ra0 * rx0;
+  const int ncols = n * ra1 * rx1;
+  const double *Ak = A.data + A.off[k];
+  const double *xk = x.data + x.off[k];
+  double *yk = y.data + y.off[k];
+  const int tx = threadIdx.x % MV_TX, ty = threadIdx.x / MV_TX;
+  for (int col = blockIdx.x; col < ncols; col += gridDim.x) {
+    const int i = col % n;
+    const int s = col / n;
+    const int c = s / rx1;
+    const int d = s - c * rx1;
+    double *ycol = yk + (int64_t)P * col;
+    for (int b0 = 0; b0 < rx0; b0 += MV_TX) {
+      const int b = b0 + tx;
+      const bool act = b < rx0;
+      float xv[MV_MMAX];
+#pragma unroll
+      for (int j = 0; j < MV_MMAX; ++j)
+        xv[j] = (act && j < m)
+                    ? to_compute<T>(xk[b + (int64_t)rx0 * (j + m * d)])
+                    : 0.0f;
+      for (int a = ty; a < ra0; a += MV_TY) {
+        const double *Aa = Ak + a + (int64_t)ra0 * (i + (int64_t)n * m * c);
+        float acc = 0.0f;
+#pragma unroll
+        for (int j = 0; j < MV_MMAX; ++j)
+          if (j < m) acc = fmaf(to_compute<T>(Aa[(int64_t)ra0 * n * j]), xv[j], acc);
+        if (act) ycol[a * rx0 + b] = static_cast<double>(acc);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ int64_t core_elems(const int *rk, const TTView &v,
+                                              int k) {
+  return (int64_t)rk[k] * v.n[k] * v.m[k] * rk[k + 1];
+}
+
+// packed <-> slotted: block y = core, grid-stride over elements
+__global__ void k_pack(TTView v, double *packed, int to_packed) {
+  const int k = blockIdx.y;
+  int64_t off = 0;
+  for (int l = 0; l < k; ++l) off += core_elems(v.rk, v, l);
+  const int64_t ne = core_elems(v.rk, v, k);
+  double *slot = v.data + v.off[k];
+  double *pk = packed + off;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (to_packed)
+      pk[e] = slot[e];
+    else
+      slot[e] = pk[e];
+  }
+}
+
+__global__ void k_copy_tt(TTView a, TTView b) {
+  const int k = blockIdx.y;
+  if (blockIdx.x == 0 && k == 0 && threadIdx.x <= a.D)
+    b.rk[threadIdx.x] = a.rk[threadIdx.x];
+  const int64_t ne = core_elems(a.rk, a, k);
+  const double *src = a.data + a.off[k];
+  double *dst = b.data + b.off[k];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = src[e];
+}
+
+// z = a x + b y.  Core k of z has ranks (rx0+ry0, rx1+ry1) except at the
+// ends; the scalars multiply the first core only.
+__global__ void k_axpby(double a, const double *a_dev, TTView x, double b,
+                        const double *b_dev, TTView y, TTView z) {
+  const int k = blockIdx.y;
+  const int D = x.D;
+  const int rx0 = x.rk[k], rx1 = x.rk[k + 1];
+  const int ry0 = y.rk[k], ry1 = y.rk[k + 1];
+  if (blockIdx.x == 0 && k == 0 && threadIdx.x <= D) {
+    const int t = threadIdx.x;
+    z.rk[t] = (t == 0 || t == D) ? 1 : x.rk[t] + y.rk[t];
+  }
+  const double ca = a * (a_dev ? *a_dev : 1.0);
+  const double cb = b * (b_dev ? *b_dev : 1.0);
+  const int nm = x.n[k] * x.m[k];
+  const int rz0 = (k == 0) ? 1 : rx0 + ry0;
+  const int rz1 = (k == D - 1) ? 1 : rx1 + ry1;
+  const int64_t ne = (int64_t)rz0 * nm * rz1;
+  const double *xk = x.data + x.off[k];
+  const double *yk = y.data + y.off[k];
+  double *zk = z.data + z.off[k];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int p = (int)(e % rz0);
+    const int64_t rest = e / rz0;
+    const int i = (int)(rest % nm);
+    const int q = (int)(rest / nm);
+    double v;
+    if (D == 1) {
+      v = ca * xk[i] + cb * yk[i];
+    } else if (k == 0) {
+      v = (q < rx1) ? ca * xk[i + (int64_t)nm * q]
+                    : cb * yk[i + (int64_t)nm * (q - rx1)];
+    } else if (k == D - 1) {
+      v = (p < rx0) ? xk[p + (int64_t)rx0 * i] : yk[(p - rx0) + (int64_t)ry0 * i];
+    } else {
+      const bool inx = p < rx0, iny = q >= rx1;
+      if (inx && !iny)
+        v = xk[p + (int64_t)rx0 * (i + (int64_t)nm * q)];
+      else if (!inx && iny)
+        v = yk[(p - rx0) + (int64_t)ry0 * (i + (int64_t)nm * (q - rx1))];
+      else
+        v = 0.0;
+    }
+    zk[e] = v;
+  }
+}
+
+// <x, y>: left environment Phi_{k+1} = sum_i x_k(:,i,:)^T Phi_k y_k(:,i,:),
+// computed by one block; Phi and the intermediate T live in `ws`.
+constexpr int DOT_THREADS = 1024;
+__global__ void __launch_bounds__(DOT_THREADS)
+    k_dot(TTView x, TTView y, double *out, double *ws, int64_t phi_cap) {
+  double *phi = ws;
+  double *T = ws + phi_cap;
+  const int D = x.D;
+  if (threadIdx.x == 0) phi[0] = 1.0;
+  __syncthreads();
+  for (int k = 0; k < D; ++k) {
+    const int rx0 = x.rk[k], rx1 = x.rk[k + 1];
+    const int ry0 = y.rk[k], ry1 = y.rk[k + 1];
+    const int n = x.n[k] * x.m[k];
+    const double *xk = x.data + x.off[k];
+    const double *yk = y.data + y.off[k];
+    // T[a, i, b'] = sum_a' phi[a, a'] y[a', i, b']   (rx0 x n*ry1)
+    const int tn = rx0 * n * ry1;
+    for (int e = threadIdx.x; e < tn; e += blockDim.x) {
+      const int a = e % rx0;
+      const int col = e / rx0;  // i + n b'
+      const double *ycol = yk + (int64_t)ry0 * col;
+      double acc = 0.0;
+      for (int a2 = 0; a2 < ry0; ++a2) acc = fma(phi[a + rx0 * a2], ycol[a2], acc);
+      T[e] = acc;
+    }
+    __syncthreads();
+    // phi'[b, b'] = sum_{a,i} x[a, i, b] T[a, i, b']   (rx1 x ry1)
+    const int pn = rx1 * ry1;
+    const int L = rx0 * n;
+    for (int e = threadIdx.x; e < pn; e += blockDim.x) {
+      const int b = e % rx1, b2 = e / rx1;
+      const double *xc = xk + (int64_t)L * b;
+      const double *tc = T + (int64_t)L * b2;
+      double acc = 0.0;
+      for (int l = 0; l < L; ++l) acc = fma(xc[l], tc[l], acc);
+      phi[b + rx1 * b2] = acc;  // read of old phi finished before the barrier
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = phi[0];
+}
+
+__global__ void k_scalar(int op, double *s0, const double *s1,
+                         const double *s2, double c) {
+  switch (op) {
+    case SC_DIV: *s0 = *s1 / *s2; break;
+    case SC_NEG: *s0 = -*s1; break;
+    case SC_COPY: *s0 = *s1; break;
+    case SC_SQRT_DIV: *s0 = sqrt(fmax(*s1, 0.0)) / c; break;
+    case SC_SET: *s0 = c; break;
+  }
+}
+
+int max_cols(const TTView &v) {
+  int mx = 1;
+  for (int k = 0; k < v.D; ++k) {
+    int c = v.n[k] * v.cap[k + 1];
+    mx = c > mx ? c : mx;
+  }
+  return mx;
+}
+
+int64_t max_core_cap(const TTView &v) {
+  int64_t mx = 1;
+  for (int k = 0; k < v.D; ++k) {
+    int64_t c = (int64_t)v.cap[k] * v.n[k] * v.m[k] * v.cap[k + 1];
+    mx = c > mx ? c : mx;
+  }
+  return mx;
+}
+
+}  // namespace
+
+hipError_t launch_matvec(const TTView &A, const TTView &x, const TTView &y,
+                         qtt_dtype compute, hipStream_t s) {
+  int cols = 1;
+  for (int k = 0; k < A.D; ++k) {
+    int c = A.n[k] * A.cap[k + 1] * x.cap[k + 1];
+    cols = c > cols ? c : cols;
+  }
+  cols = cols < 65535 ? cols : 65535;
+  dim3 grid(cols, A.D);
+  dim3 block(MV_TX * MV_TY);
+  if (compute == QTT_F64)
+    hipLaunchKernelGGL(k_matvec_f64, grid, block, 0, s, A, x, y);
+  else if (compute == QTT_F32)
+    hipLaunchKernelGGL(k_matvec_lp<float>, grid, block, 0, s, A, x, y);
+  else
+    hipLaunchKernelGGL(k_matvec_lp<__hip_bfloat16>, grid, block, 0, s, A, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const double *packed, const TTView &dst,
+                         hipStream_t s) {
+  int64_t mc = max_core_cap(dst);
+  int blocks = (int)((mc + 255) / 256);
+  blocks = blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096;
+  hipLaunchKernelGGL(k_pack, dim3(blocks, dst.D), dim3(256), 0, s, dst,
+                     const_cast<double *>(packed), 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const TTView &src, double *packed, hipStream_t s) {
+  int64_t mc = max_core_cap(src);
+  int blocks = (int)((mc + 255) / 256);
+  blocks = blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096;
+  hipLaunchKernelGGL(k_pack, dim3(blocks, src.D), dim3(256), 0, s, src,
+                     packed, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_tt(const TTView &src, const TTView &dst,
+                          hipStream_t s) {
+  int64_t mc = max_core_cap(src);
+  int blocks = (int)((mc + 255) / 256);
+  blocks = blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096;
+  hipLaunchKernelGGL(k_copy_tt, dim3(blocks, src.D), dim3(256), 0, s, src,
+                     dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(double a, const double *a_dev, const TTView &x,
+                        double b, const double *b_dev, const TTView &y,
+                        const TTView &z, hipStream_t s) {
+  int64_t mc = max_core_cap(z);
+  int blocks = (int)((mc + 255) / 256);
+  blocks = blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096;
+  hipLaunchKernelGGL(k_axpby, dim3(blocks, x.D), dim3(256), 0, s, a, a_dev,
+                     x, b, b_dev, y, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(const TTView &x, const TTView &y, double *out,
+                      double *ws, int64_t ws_elems, hipStream_t s) {
+  int64_t phi_cap = 1;
+  for (int k = 0; k <= x.D; ++k) {
+    int64_t c = (int64_t)x.cap[k] * y.cap[k];
+    phi_cap = c > phi_cap ? c : phi_cap;
+  }
+  hipLaunchKernelGGL(k_dot, dim3(1), dim3(DOT_THREADS), 0, s, x, y, out, ws,
+                     phi_cap);
+  return hipGetLastError();
+}
+
+int64_t dot_ws_elems(const TTView &x, const TTView &y) {
+  int64_t phi_cap = 1, t_cap = 1;
+  for (int k = 0; k <= x.D; ++k) {
+    int64_t c = (int64_t)x.cap[k] * y.cap[k];
+    phi_cap = c > phi_cap ? c : phi_cap;
+  }
+  for (int k = 0; k < x.D; ++k) {
+    int64_t c = (int64_t)x.cap[k] * x.n[k] * x.m[k] * y.cap[k + 1];
+    t_cap = c > t_cap ? c : t_cap;
+  }
+  return phi_cap + t_cap;
+}
+
+hipError_t launch_scalar(int op, double *s0, const double *s1,
+                         const double *s2, double c, hipStream_t s) {
+  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(1), 0, s, op, s0, s1, s2, c);
+  return hipGetLastError();
+}
+
+namespace {
+struct RankArg {
+  int D;
+  int r[QTT_MAXD + 1];
+};
+__global__ void k_set_ranks(int *rk, RankArg a) {
+  if ((int)threadIdx.x <= a.D) rk[threadIdx.x] = a.r[threadIdx.x];
+}
+}  // namespace
+
+// ranks travel as a kernel argument, so the host array may be reused at once
+hipError_t upload_ranks(const TTView &v, const int32_t *ranks,
+                        hipStream_t s) {
+  RankArg a;
+  a.D = v.D;
+  for (int k = 0; k <= v.D; ++k) a.r[k] = ranks[k];
+  hipLaunchKernelGGL(k_set_ranks, dim3(1), dim3(64), 0, s, v.rk, a);
+  return hipGetLastError();
+}
+
+}  // namespace qtt

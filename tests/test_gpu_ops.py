@@ -1,0 +1,152 @@
+"""Parity of the HIP tensor-train operations with the FP64 CPU oracle, through
+the C ABI, on seeded random tensor trains (several tiles, ragged ranks, odd
+modes) and at the bond shapes of the level-10 workload."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import qtt as T
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2501_07778_amd as P
+    return P
+
+
+def _vec(seed, modes, r):
+    return W.random_tt_cores(seed, modes, W.capped_ranks(modes, r))
+
+
+def _mat(seed, modes, r):
+    ranks = W.capped_ranks([m * m for m in modes], r)
+    return W.random_tt_cores(seed, modes, ranks, ncol=modes)
+
+
+CASES = [
+    ([2, 2, 2, 2, 2], 3, 4),
+    ([2, 3, 2, 2, 2, 2], 5, 7),
+    ([2, 2, 2, 2, 2, 2, 2, 2, 2], 9, 33),    # ragged: 33 spans several 64-lanes
+    ([2] * 11, 25, 70),                     # ranks beyond one wave along b
+    ([2], 1, 1),
+]
+
+
+@pytest.mark.parametrize("modes,ra,rx", CASES)
+@pytest.mark.parametrize("compute", ["f64"])
+def test_matvec_cores_bit_close(P, modes, ra, rx, compute):
+    A = _mat(1, modes, ra)
+    x = _vec(2, modes, rx)
+    y_ref = T.matvec(A, x)
+    y = P.matvec(P.tt_from_cores(A), P.tt_from_cores(x), compute)
+    assert y.ranks == T.ranks(y_ref)
+    got = P.tt_to_cores(y)
+    for g, r in zip(got, y_ref):
+        # each output is a sum of m products: equal up to the order of rounding
+        scale = np.abs(r).max() + 1e-300
+        assert np.abs(g - r).max() <= 4e-16 * scale * 4
+
+
+@pytest.mark.parametrize("compute,tol", [("f32", 2e-6), ("bf16", 2e-2)])
+def test_matvec_low_precision(P, compute, tol):
+    modes = [2] * 9
+    A = _mat(3, modes, 7)
+    x = _vec(4, modes, 12)
+    y_ref = T.full_vector(T.matvec(A, x))
+    y = P.matvec(P.tt_from_cores(A), P.tt_from_cores(x), compute)
+    yd = T.full_vector(P.tt_to_cores(y))
+    assert np.linalg.norm(yd - y_ref) <= tol * np.linalg.norm(y_ref)
+
+
+@pytest.mark.parametrize("modes,r,eps,rmax", [
+    ([2] * 6, 5, 1e-10, 0),
+    ([2, 3, 2, 2, 2, 2, 2], 9, 1e-6, 0),
+    ([2] * 10, 20, 1e-3, 0),
+    ([2] * 10, 20, 0.0, 6),
+    ([4] * 5, 12, 1e-8, 0),
+    ([2] * 8, 70, 1e-12, 0),                 # unfoldings larger than a tile
+])
+def test_round_matches_oracle(P, modes, r, eps, rmax):
+    y = _vec(7, modes, r)
+    ref, info = T.tt_round(y, eps, rmax if rmax > 0 else 1 << 30, return_info=True)
+    t = P.tt_from_cores(y)
+    nrm, err = P.round_(t, eps, rmax)
+    got = P.tt_to_cores(t)
+    yd = T.full_vector(y)
+    gd = T.full_vector(got)
+    rd = T.full_vector(ref)
+    assert nrm == pytest.approx(info["norm"], rel=1e-12)
+    # rounding guarantee against the exact tensor
+    if rmax == 0:
+        assert np.linalg.norm(gd - yd) <= eps * np.linalg.norm(yd) * (1 + 1e-8) + 1e-13 * np.linalg.norm(yd)
+    # same tensor as the oracle up to FP64 noise (gauge-free comparison)
+    assert np.linalg.norm(gd - rd) <= 1e-11 * np.linalg.norm(yd) + 2 * max(err, info["err"])
+    # ranks: equal, or off by one at a near-tie of singular values
+    for a, b in zip(t.ranks, T.ranks(ref)):
+        assert abs(a - b) <= 1
+    assert err == pytest.approx(info["err"], rel=1e-6, abs=1e-13 * np.linalg.norm(yd))
+    # result is right-orthogonal except the first core
+    for c in got[1:]:
+        M = c.reshape(c.shape[0], -1, order="F")
+        np.testing.assert_allclose(M @ M.T, np.eye(c.shape[0]), atol=1e-12)
+
+
+def test_round_of_matvec_product(P):
+    """The hot-path combination: round(K x) against the oracle."""
+    from oracle import assembly as A
+    prob = W.cantilever_traction(4)
+    Kq, fq = A.assemble_qtt(prob)
+    x = T.tt_round(fq, 1e-12)
+    ref, info = T.tt_round(T.matvec(Kq, x), 1e-8, return_info=True)
+    y = P.matvec(P.tt_from_cores(Kq), P.tt_from_cores(x))
+    nrm, err = P.round_(y, 1e-8)
+    gd = T.full_vector(P.tt_to_cores(y))
+    rd = T.full_vector(ref)
+    assert nrm == pytest.approx(info["norm"], rel=1e-12)
+    assert np.linalg.norm(gd - rd) <= 2e-8 * np.linalg.norm(rd)
+
+
+def test_round_zero_and_single_core(P):
+    y = [np.zeros((1, 2, 3)), np.zeros((3, 2, 2)), np.zeros((2, 2, 1))]
+    t = P.tt_from_cores(y)
+    nrm, err = P.round_(t, 1e-8)
+    assert nrm == 0.0 and t.ranks == [1, 1, 1, 1]
+    assert np.all(T.full_vector(P.tt_to_cores(t)) == 0)
+    one = [np.arange(6, dtype=float).reshape(1, 6, 1)]
+    t = P.tt_from_cores(one)
+    nrm, _ = P.round_(t, 1e-8)
+    assert nrm == pytest.approx(np.linalg.norm(np.arange(6)))
+
+
+@pytest.mark.parametrize("modes,r1,r2", [([2] * 7, 5, 9), ([2, 3, 2, 2], 2, 3), ([2] * 12, 40, 17)])
+def test_dot_and_axpby(P, modes, r1, r2):
+    x = _vec(11, modes, r1)
+    y = _vec(12, modes, r2)
+    tx, ty = P.tt_from_cores(x), P.tt_from_cores(y)
+    assert P.dot(tx, ty) == pytest.approx(T.dot(x, y), rel=1e-12, abs=1e-14)
+    z = P.axpby(0.5, tx, -2.0, ty)
+    ref = T.add(x, y, coeffs=[0.5, -2.0])
+    assert z.ranks == T.ranks(ref)
+    for g, r in zip(P.tt_to_cores(z), ref):
+        np.testing.assert_array_equal(g, r)
+
+
+def test_matvec_level10_shapes_sampled(P):
+    """Full-size bond shapes of the level-10 traction workload (operator rank
+    25, vector rank 64, 21 cores): cores of the product checked on sampled
+    cores against the oracle's formula, computed one core at a time."""
+    from oracle import assembly as A
+    Kq, _ = A.assemble_qtt(W.cantilever_traction(10))
+    modes = [2] * 21
+    x = W.random_tt_cores(5, modes, W.capped_ranks(modes, 64))
+    y = P.matvec(P.tt_from_cores(Kq), P.tt_from_cores(x))
+    got = P.tt_to_cores(y)
+    for k in (0, 1, 7, 10, 15, 20):
+        ref = T.matvec([Kq[k]], [x[k]])[0]
+        assert np.abs(got[k] - ref).max() <= 2e-15 * np.abs(ref).max()

@@ -1,0 +1,60 @@
+"""Host-side checks of the C-ABI library: it loads without a GPU and exports
+every function declared in include/qtt.h; host validation rejects bad input
+before any device work."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2501_07778_amd", "libqtt.so")
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(qtt_[a-z_0-9]+)\s*\(", txt))
+    return names
+
+
+def test_header_declares_the_four_calls():
+    d = _declared()
+    for n in ("qtt_assemble_stiffness", "qtt_matvec", "qtt_round", "qtt_solve"):
+        assert n in d
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.skip("libqtt.so not built")
+    lib = C.CDLL(LIB)
+    for n in sorted(_declared()):
+        assert hasattr(lib, n), n
+
+
+def test_host_validation_without_gpu():
+    if not os.path.exists(LIB):
+        pytest.skip("libqtt.so not built")
+    import paper_2501_07778_amd as P
+    L = P.lib()
+    # NULL operands and bad shapes are rejected on the host with a message
+    assert L.qtt_matvec(None, None, None, 0, None, 0, None) == -1
+    assert b"NULL" in L.qtt_last_error()
+    nrow = (C.c_int32 * 2)(2, 2)
+    ranks = (C.c_int32 * 3)(1, 3, 2)    # last rank must be 1
+    t = P._lib._TT(2, nrow, None, ranks, None, 100)
+    need = C.c_size_t()
+    assert L.qtt_round(C.byref(t), 1e-8, 0, None, None, None, 0, None) == -2
+    assert b"boundary" in L.qtt_last_error()
+    ranks[2] = 1
+    t.capacity = 3                      # needs 1*2*3 + 3*2*1 = 12
+    t.data = 12345                      # never dereferenced: validation fails first
+    assert L.qtt_round(C.byref(t), 1e-8, 0, None, None, None, 0, None) == -3
+    t.capacity = 12
+    assert L.qtt_round_workspace(C.byref(t), 0, C.byref(need)) == 0 and need.value > 0
+    # a workspace that is too small is reported, not used
+    assert L.qtt_round(C.byref(t), 1e-8, 0, None, None, None, 16, None) == -3
+    assert L.qtt_version().startswith(b"qtt")
