@@ -111,7 +111,9 @@ enum ScalarOp {
   SC_NEG = 1,        // s0 = -s1
   SC_COPY = 2,       // s0 = s1
   SC_SQRT_DIV = 3,   // s0 = sqrt(max(s1,0)) / c
-  SC_SET = 4         // s0 = c
+  SC_SET = 4,        // s0 = c
+  SC_DIV_POS = 5,    // s0 = s2 > 0 ? s1 / s2 : 0
+  SC_NORM2 = 6       // s0 = s1[0]^2 - s1[1] (squared norm after truncation)
 };
 
 // rounding (exact algorithm); ws sized by round_workspace_elems

@@ -247,6 +247,8 @@ __global__ void k_scalar(int op, double *s0, const double *s1,
     case SC_COPY: *s0 = *s1; break;
     case SC_SQRT_DIV: *s0 = sqrt(fmax(*s1, 0.0)) / c; break;
     case SC_SET: *s0 = c; break;
+    case SC_DIV_POS: *s0 = (*s2 > 0.0) ? *s1 / *s2 : 0.0; break;
+    case SC_NORM2: *s0 = fmax(s1[0] * s1[0] - s1[1], 0.0); break;
   }
 }
 

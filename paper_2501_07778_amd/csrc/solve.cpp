@@ -1,3 +1,316 @@
+// solve.cpp — qtt_solve: conjugate gradients on the QTT format with FP64
+// iterative refinement, driven by the QTT matrix-vector product and TT
+// rounding.
+//
+// The paper solves K u = f with AMEn (Sec. 3.5, Sec. 4), which it cites but
+// does not describe; this solve is built from the two operations of the
+// format instead:
+//   outer (FP64):  r = round(f - K u); stop when ||f - K u|| <= tol ||f||
+//                  (the norm of the unrounded difference comes out of the
+//                  rounding's QR sweep); e = CG(K, r); u = round(u + e)
+//   inner:         CG with every iterate, residual, direction and product
+//                  K p rounded to (eps_in, rmax_in); ||r||^2 is read off the
+//                  rounding of r (norm^2 minus the discarded sigma^2).
+// All scalars and ranks stay on the device; the host synchronises only at
+// the convergence checks (every check_every inner iterations and once per
+// refinement step).
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
 #include "internal.h"
-extern "C" qtt_status qtt_solve(const qtt_tt *, const qtt_tt *, const qtt_tt *, const qtt_solve_opts *, qtt_tt *, qtt_solve_report *, void *, size_t, void *) { return QTT_E_UNSUPPORTED; }
-extern "C" qtt_status qtt_solve_workspace(const qtt_tt *, const qtt_tt *, const qtt_solve_opts *, size_t *) { return QTT_E_UNSUPPORTED; }
+
+namespace qtt {
+namespace {
+
+struct SolveLayout {
+  TTDesc U[2], Ku, R, X[2], Rr[2], Pp[2], Q;
+  RoundWs rw;
+  double *dot_ws = nullptr;
+  int64_t dot_elems = 0;
+  double *sc = nullptr;  // device scalars
+};
+
+enum {
+  S_FNORM2 = 0, S_RHO, S_PQ, S_ALPHA, S_BETA, S_RHONEW, S_ONE, S_RES, S_COUNT = 16
+};
+
+std::vector<int> caps_for(const qtt_tt *K, int r) {
+  return bounded_caps(K->ncores, K->nrow, nullptr, r);
+}
+
+bool carve(Arena &ar, const qtt_tt *K, const qtt_tt *f, const qtt_solve_opts *o,
+           SolveLayout &L) {
+  const int D = K->ncores;
+  const int32_t *n = K->nrow;
+  int Rk = 1;
+  for (int k = 0; k <= D; ++k) Rk = K->ranks[k] > Rk ? K->ranks[k] : Rk;
+  int rf = 1;
+  for (int k = 0; k <= D; ++k) rf = f->ranks[k] > rf ? f->ranks[k] : rf;
+  const int rmax = o->rmax, rin = o->rmax_in;
+  // products have ranks R_k * r_k bond by bond
+  auto prod_caps = [&](int r) {
+    std::vector<int> c = caps_for(K, r);
+    for (int k = 0; k <= D; ++k) c[k] *= K->ranks[k];
+    return c;
+  };
+  auto sum_caps = [&](std::vector<int> a, const std::vector<int> &b) {
+    for (size_t k = 0; k < a.size(); ++k) a[k] += b[k];
+    a.front() = a.back() = 1;
+    return a;
+  };
+  std::vector<int> cu = caps_for(K, rmax), ci = caps_for(K, rin);
+  std::vector<int> cf(f->ranks, f->ranks + D + 1);
+  bool ok = true;
+  for (int s = 0; s < 2; ++s) ok &= arena_tt(ar, L.U[s], D, n, nullptr, sum_caps(cu, ci));
+  ok &= arena_tt(ar, L.Ku, D, n, nullptr, prod_caps(rmax));
+  std::vector<int> cr = sum_caps(prod_caps(rmax), cf);
+  ok &= arena_tt(ar, L.R, D, n, nullptr, sum_caps(cr, ci));
+  std::vector<int> c2 = sum_caps(sum_caps(ci, ci), ci);
+  for (int s = 0; s < 2; ++s) {
+    ok &= arena_tt(ar, L.X[s], D, n, nullptr, c2);
+    ok &= arena_tt(ar, L.Rr[s], D, n, nullptr, sum_caps(ci, prod_caps(rin)));
+    ok &= arena_tt(ar, L.Pp[s], D, n, nullptr, c2);
+  }
+  ok &= arena_tt(ar, L.Q, D, n, nullptr, prod_caps(rin));
+  // the rounding workspace serves every operand: size it for the bondwise
+  // largest caps
+  TTView big = L.R.v;
+  for (const TTDesc *t : {&L.U[0], &L.Ku, &L.X[0], &L.Rr[0], &L.Pp[0], &L.Q})
+    for (int k = 0; k <= D; ++k) big.cap[k] = big.cap[k] > t->v.cap[k] ? big.cap[k] : t->v.cap[k];
+  ok &= round_ws_take(ar, big, L.rw);
+  TTView fv = L.R.v;
+  for (int k = 0; k <= D; ++k) fv.cap[k] = cf[k];
+  L.dot_elems = dot_ws_elems(L.R.v, L.R.v);
+  for (int64_t e : {dot_ws_elems(fv, fv), dot_ws_elems(L.Pp[0].v, L.Q.v)})
+    L.dot_elems = e > L.dot_elems ? e : L.dot_elems;
+  L.dot_ws = (double *)ar.take(sizeof(double) * L.dot_elems);
+  L.sc = (double *)ar.take(sizeof(double) * S_COUNT);
+  (void)Rk;
+  (void)rf;
+  return ok && ar.ok();
+}
+
+void packed_view_of(const qtt_tt *t, TTView &v, int32_t *rk) {
+  v.D = t->ncores;
+  int64_t off = 0;
+  for (int k = 0; k < t->ncores; ++k) {
+    v.n[k] = t->nrow[k];
+    v.m[k] = t->ncol ? t->ncol[k] : 1;
+    v.off[k] = off;
+    off += (int64_t)t->ranks[k] * v.n[k] * v.m[k] * t->ranks[k + 1];
+  }
+  for (int k = 0; k <= t->ncores; ++k) v.cap[k] = t->ranks[k];
+  for (int k = t->ncores; k < QTT_MAXD; ++k) {
+    v.n[k] = 1;
+    v.m[k] = 1;
+    v.off[k] = off;
+  }
+  v.rk = rk;
+  v.data = t->data;
+}
+
+qtt_status check_opts(const qtt_solve_opts *o) {
+  if (!o) return fail(QTT_E_INVAL, "opts is NULL");
+  if (!(o->tol > 0.0) || !(o->eps >= 0.0) || !(o->eps_in >= 0.0) || !(o->red_in > 0.0))
+    return fail(QTT_E_INVAL, "tolerances must be positive");
+  if (o->rmax < 1 || o->rmax_in < 1 || o->rmax > 4096 || o->rmax_in > 4096)
+    return fail(QTT_E_INVAL, "rank caps must be in 1..4096");
+  if (o->maxit_in < 1 || o->maxit_out < 0) return fail(QTT_E_INVAL, "bad iteration limits");
+  if (o->compute != QTT_F64 && o->compute != QTT_F32 && o->compute != QTT_BF16)
+    return fail(QTT_E_INVAL, "bad compute dtype");
+  if (o->sketch != 0) return fail(QTT_E_UNSUPPORTED, "sketched rounding is not available");
+  return QTT_OK;
+}
+
+qtt_status check_system(const qtt_tt *K, const qtt_tt *f) {
+  if (!K || !f || !K->ncol || f->ncol) return fail(QTT_E_INVAL, "K must be a matrix, f a vector");
+  if (K->ncores != f->ncores || K->ncores < 1 || K->ncores > QTT_MAX_CORES)
+    return fail(QTT_E_SHAPE, "core counts differ");
+  for (int k = 0; k < K->ncores; ++k)
+    if (K->nrow[k] != K->ncol[k] || K->nrow[k] != f->nrow[k])
+      return fail(QTT_E_SHAPE, "K must be square with f's modes");
+  if (K->ranks[0] != 1 || K->ranks[K->ncores] != 1 || f->ranks[0] != 1 || f->ranks[f->ncores] != 1)
+    return fail(QTT_E_SHAPE, "boundary ranks must be 1");
+  if (!K->data || !f->data) return fail(QTT_E_INVAL, "NULL data");
+  return QTT_OK;
+}
+
+}  // namespace
+}  // namespace qtt
+
+using namespace qtt;
+
+extern "C" qtt_status qtt_solve_workspace(const qtt_tt *K, const qtt_tt *f,
+                                          const qtt_solve_opts *o, size_t *bytes) {
+  qtt_status st;
+  if ((st = check_system(K, f)) != QTT_OK) return st;
+  if ((st = check_opts(o)) != QTT_OK) return st;
+  if (!bytes) return fail(QTT_E_INVAL, "bytes is NULL");
+  Arena ar;
+  ar.dry = true;
+  SolveLayout L;
+  carve(ar, K, f, o, L);
+  ar.take(sizeof(int32_t) * 3 * (QTT_MAXD + 1));
+  *bytes = ar.used + 4096;
+  return QTT_OK;
+}
+
+extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
+                                const qtt_solve_opts *o, qtt_tt *u, qtt_solve_report *rep,
+                                void *ws, size_t ws_bytes, void *stream) {
+  qtt_status st;
+  if ((st = check_system(K, f)) != QTT_OK) return st;
+  if ((st = check_opts(o)) != QTT_OK) return st;
+  if (!u || !u->data || !u->ranks || u->ncores != K->ncores) return fail(QTT_E_INVAL, "bad u");
+  if (x0) {
+    if (x0->ncores != K->ncores || x0->ncol || !x0->data) return fail(QTT_E_SHAPE, "bad x0");
+    std::vector<int> cu = bounded_caps(K->ncores, K->nrow, nullptr, o->rmax);
+    for (int k = 0; k <= x0->ncores; ++k)
+      if (x0->ranks[k] > cu[k])
+        return fail(QTT_E_SHAPE, "x0 rank exceeds rmax or the mode-product bound");
+  }
+  if (!ws) return fail(QTT_E_CAPACITY, "workspace is NULL");
+  Arena ar;
+  ar.base = (char *)ws;
+  ar.size = ws_bytes;
+  SolveLayout L;
+  if (!carve(ar, K, f, o, L)) return fail(QTT_E_CAPACITY, "solve workspace too small");
+  int32_t *rk = (int32_t *)ar.take(sizeof(int32_t) * 3 * (QTT_MAXD + 1));
+  if (!ar.ok()) return fail(QTT_E_CAPACITY, "solve workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  const int D = K->ncores;
+  TTView Kv, fv, x0v;
+  packed_view_of(K, Kv, rk);
+  packed_view_of(f, fv, rk + (QTT_MAXD + 1));
+  QTT_HIP(upload_ranks(Kv, K->ranks, s));
+  QTT_HIP(upload_ranks(fv, f->ranks, s));
+  double *sc = L.sc;
+  const RoundWs &rw = L.rw;
+  QTT_HIP(launch_scalar(SC_SET, sc + S_ONE, nullptr, nullptr, 1.0, s));
+  QTT_HIP(launch_dot(fv, fv, sc + S_FNORM2, L.dot_ws, L.dot_elems, s));
+  double fn2 = 0.0;
+  QTT_HIP(hipMemcpyAsync(&fn2, sc + S_FNORM2, sizeof(double), hipMemcpyDeviceToHost, s));
+  QTT_HIP(hipStreamSynchronize(s));
+  const double fnorm = std::sqrt(fn2 > 0.0 ? fn2 : 0.0);
+  qtt_solve_report R;
+  std::memset(&R, 0, sizeof(R));
+  int cur = 0;
+  bool have_u = false;
+  if (x0) {
+    packed_view_of(x0, x0v, rk + 2 * (QTT_MAXD + 1));
+    QTT_HIP(upload_ranks(x0v, x0->ranks, s));
+    QTT_HIP(launch_copy_tt(x0v, L.U[0].v, s));
+    have_u = true;
+  }
+  if (fnorm == 0.0) {
+    // zero load: u = 0
+    std::vector<int32_t> ones(D + 1, 1);
+    QTT_HIP(upload_ranks(L.U[0].v, ones.data(), s));
+    QTT_HIP(hipMemsetAsync(L.U[0].v.data, 0, sizeof(double) * L.U[0].elems, s));
+    have_u = true;
+  }
+  const qtt_dtype lowp = (qtt_dtype)o->compute;
+  bool converged = fnorm == 0.0;
+  for (int out = 0; out <= o->maxit_out && fnorm > 0.0; ++out) {
+    // residual r = f - K u (exact product and difference), then rounding
+    if (have_u) {
+      QTT_HIP(launch_matvec(Kv, L.U[cur].v, L.Ku.v, QTT_F64, s));
+      QTT_HIP(launch_axpby(1.0, nullptr, fv, -1.0, nullptr, L.Ku.v, L.R.v, s));
+    } else {
+      QTT_HIP(launch_copy_tt(fv, L.R.v, s));
+    }
+    QTT_HIP(round_tt(L.R.v, o->eps_in, o->rmax_in, rw, s));
+    double nr[2];
+    QTT_HIP(hipMemcpyAsync(nr, rw.scal, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+    QTT_HIP(hipStreamSynchronize(s));
+    const double rel = nr[0] / fnorm;
+    if (out < 64) R.residual_hist[out] = rel;
+    R.residual = rel;
+    if (!std::isfinite(rel)) return fail(QTT_E_NOCONV, "residual is not finite");
+    if (rel <= o->tol) {
+      converged = true;
+      break;
+    }
+    if (out == o->maxit_out) break;
+    // inner CG on K e = r: x = 0, r_c = r, p = r
+    int xi = 0, ri = 0, pi = 0;
+    {
+      std::vector<int32_t> ones(D + 1, 1);
+      QTT_HIP(upload_ranks(L.X[0].v, ones.data(), s));
+      QTT_HIP(hipMemsetAsync(L.X[0].v.data, 0, sizeof(double) * L.X[0].elems, s));
+    }
+    QTT_HIP(launch_copy_tt(L.R.v, L.Rr[0].v, s));
+    QTT_HIP(launch_copy_tt(L.R.v, L.Pp[0].v, s));
+    // rho = ||r||^2 after the rounding above
+    QTT_HIP(launch_scalar(SC_NORM2, sc + S_RHO, rw.scal, nullptr, 0.0, s));
+    const double bn = nr[0] * std::sqrt(std::fmax(1.0 - (nr[1] / (nr[0] * nr[0] + 1e-300)), 0.0));
+    int it = 0;
+    for (it = 1; it <= o->maxit_in; ++it) {
+      // q = round(K p)
+      QTT_HIP(launch_matvec(Kv, L.Pp[pi].v, L.Q.v, lowp, s));
+      QTT_HIP(round_tt(L.Q.v, o->eps_in, o->rmax_in, rw, s));
+      QTT_HIP(launch_dot(L.Pp[pi].v, L.Q.v, sc + S_PQ, L.dot_ws, L.dot_elems, s));
+      QTT_HIP(launch_scalar(SC_DIV_POS, sc + S_ALPHA, sc + S_RHO, sc + S_PQ, 0.0, s));
+      // x = round(x + alpha p)
+      QTT_HIP(launch_axpby(1.0, nullptr, L.X[xi].v, 1.0, sc + S_ALPHA, L.Pp[pi].v, L.X[1 - xi].v, s));
+      xi = 1 - xi;
+      QTT_HIP(round_tt(L.X[xi].v, o->eps_in, o->rmax_in, rw, s));
+      // r = round(r - alpha q); rho_new = ||r||^2
+      QTT_HIP(launch_axpby(1.0, nullptr, L.Rr[ri].v, -1.0, sc + S_ALPHA, L.Q.v, L.Rr[1 - ri].v, s));
+      ri = 1 - ri;
+      QTT_HIP(round_tt(L.Rr[ri].v, o->eps_in, o->rmax_in, rw, s));
+      QTT_HIP(launch_scalar(SC_NORM2, sc + S_RHONEW, rw.scal, nullptr, 0.0, s));
+      if (it % o->check_every == 0 || it == o->maxit_in) {
+        double rho_new = 0.0;
+        QTT_HIP(hipMemcpyAsync(&rho_new, sc + S_RHONEW, sizeof(double), hipMemcpyDeviceToHost, s));
+        QTT_HIP(hipStreamSynchronize(s));
+        if (!std::isfinite(rho_new)) return fail(QTT_E_NOCONV, "inner residual is not finite");
+        if (std::sqrt(rho_new) <= o->red_in * bn) break;
+      }
+      // p = round(r + beta p)
+      QTT_HIP(launch_scalar(SC_DIV, sc + S_BETA, sc + S_RHONEW, sc + S_RHO, 0.0, s));
+      QTT_HIP(launch_axpby(1.0, nullptr, L.Rr[ri].v, 1.0, sc + S_BETA, L.Pp[pi].v, L.Pp[1 - pi].v, s));
+      pi = 1 - pi;
+      QTT_HIP(round_tt(L.Pp[pi].v, o->eps_in, o->rmax_in, rw, s));
+      QTT_HIP(launch_scalar(SC_COPY, sc + S_RHO, sc + S_RHONEW, nullptr, 0.0, s));
+    }
+    R.inner += it > o->maxit_in ? o->maxit_in : it;
+    // u = round(u + e)
+    if (have_u) {
+      QTT_HIP(launch_axpby(1.0, nullptr, L.U[cur].v, 1.0, nullptr, L.X[xi].v, L.U[1 - cur].v, s));
+      cur = 1 - cur;
+    } else {
+      QTT_HIP(launch_copy_tt(L.X[xi].v, L.U[cur].v, s));
+      have_u = true;
+    }
+    QTT_HIP(round_tt(L.U[cur].v, o->eps, o->rmax, rw, s));
+    R.outer += 1;
+  }
+  if (!have_u) {
+    std::vector<int32_t> ones(D + 1, 1);
+    QTT_HIP(upload_ranks(L.U[cur].v, ones.data(), s));
+    QTT_HIP(hipMemsetAsync(L.U[cur].v.data, 0, sizeof(double) * L.U[cur].elems, s));
+  }
+  // pack u into the caller's buffer
+  int32_t rkh[QTT_MAXD + 1];
+  QTT_HIP(hipMemcpyAsync(rkh, L.U[cur].v.rk, sizeof(int32_t) * (D + 1), hipMemcpyDeviceToHost, s));
+  QTT_HIP(hipStreamSynchronize(s));
+  int64_t need = 0;
+  for (int k = 0; k < D; ++k) need += (int64_t)rkh[k] * K->nrow[k] * rkh[k + 1];
+  if (need > u->capacity) return fail(QTT_E_CAPACITY, "u: capacity too small for the result");
+  QTT_HIP(launch_pack(L.U[cur].v, u->data, s));
+  QTT_HIP(hipStreamSynchronize(s));
+  int mr = 1;
+  for (int k = 0; k <= D; ++k) {
+    u->ranks[k] = rkh[k];
+    mr = rkh[k] > mr ? rkh[k] : mr;
+  }
+  R.max_rank = mr;
+  R.status = converged ? QTT_OK : QTT_E_NOCONV;
+  if (rep) *rep = R;
+  if (!converged) return fail(QTT_E_NOCONV, "tolerance not reached");
+  return QTT_OK;
+}

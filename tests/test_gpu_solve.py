@@ -1,0 +1,118 @@
+"""Parity of qtt_assemble_stiffness and qtt_solve (through the C ABI) with
+the FP64 oracle: the assembled QTT operator and load against the oracle's
+QTT assembly and the sparse FEM, and the solution against a sparse direct
+solve."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import assembly as A
+from oracle import fem
+from oracle import qtt as T
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2501_07778_amd as P
+    return P
+
+
+def _tt_diff_norm(a, b):
+    """||a - b||_F of two TT vectors (or matrices) via oracle dot products."""
+    if a[0].ndim == 4:
+        a, b = T.matrix_as_vector(a), T.matrix_as_vector(b)
+    d2 = T.dot(a, a) - 2 * T.dot(a, b) + T.dot(b, b)
+    return np.sqrt(max(d2, 0.0)), np.sqrt(T.dot(b, b))
+
+
+@pytest.mark.parametrize("d", [2, 3, 5])
+@pytest.mark.parametrize("which", ["body", "traction", "lshape", "lshape-paper"])
+def test_assembly_matches_sparse_fem(P, d, which):
+    if which.startswith("lshape") and d == 5:
+        d = 4
+    coupling = "paper" if which == "lshape-paper" else "symmetric"
+    prob = {"body": W.cantilever_body_force, "traction": W.cantilever_traction,
+            "lshape": W.l_shape, "lshape-paper": W.l_shape}[which](d)
+    Kt, ft = P.assemble(prob, coupling)
+    Kc, fc = P.tt_to_cores(Kt), P.tt_to_cores(ft)
+    K, f, _, _ = fem.assemble_system(prob, coupling)
+    Kz = fem.permute_matrix_to_qtt(K, d, prob.q).toarray()
+    fz = fem.to_qtt_order(f, d, prob.q)
+    np.testing.assert_allclose(T.full_matrix(Kc), Kz, atol=1e-12 * np.abs(Kz).max())
+    np.testing.assert_allclose(T.full_vector(fc), fz, atol=1e-12 * np.abs(fz).max())
+    # ranks agree with the oracle's QTT assembly (both rounded at 1e-14)
+    Ko, fo = A.assemble_qtt(prob, coupling)
+    assert max(Kt.ranks) <= max(T.ranks(Ko)) + 2
+
+
+def test_assembly_level10_against_oracle_qtt(P):
+    """Full size of the level-10 traction workload: the library's QTT
+    operator and load equal the oracle's QTT assembly in Frobenius norm."""
+    prob = W.cantilever_traction(10)
+    Kt, ft = P.assemble(prob)
+    Ko, fo = A.assemble_qtt(prob)
+    dK, nK = _tt_diff_norm(P.tt_to_cores(Kt), Ko)
+    df, nf = _tt_diff_norm(P.tt_to_cores(ft), fo)
+    assert dK <= 1e-7 * nK     # sqrt of FP64 cancellation in the dot-based norm
+    assert df <= 1e-7 * nf
+    assert max(Kt.ranks) == 25
+
+
+@pytest.mark.parametrize("d", [3, 5])
+def test_solve_body_force_matches_direct(P, d):
+    """Plain FP64 solve of the clamped unit square under body force (level 5
+    is the small workload: eps 1e-10, tolerance 1e-10)."""
+    prob = W.cantilever_body_force(d)
+    uref, _ = fem.solve_problem(prob)
+    K, f = P.assemble(prob)
+    opts = P.SolveOpts(tol=1e-10, eps=1e-10, rmax=64, eps_in=1e-3, rmax_in=32,
+                       red_in=1e-2, maxit_in=3000, maxit_out=30, check_every=5)
+    u, rep = P.solve(K, f, opts)
+    assert rep["status"] == 0, rep
+    ud = T.full_vector(P.tt_to_cores(u))
+    err = np.linalg.norm(ud - uref) / np.linalg.norm(uref)
+    assert err <= 1e-8, (err, rep)
+    # FP64 residual of the returned iterate, recomputed by the oracle
+    Ks, fs, _, _ = fem.assemble_system(prob)
+    r = fem.permute_matrix_to_qtt(Ks, d) @ ud - fem.to_qtt_order(fs, d)
+    assert np.linalg.norm(r) <= 1e-9 * np.linalg.norm(fs)
+
+
+def test_solve_traction_and_lshape(P):
+    for prob, tol in ((W.cantilever_traction(4), 1e-9), (W.l_shape(3), 1e-9)):
+        uref, _ = fem.solve_problem(prob)
+        K, f = P.assemble(prob)
+        opts = P.SolveOpts(tol=1e-11, eps=1e-11, rmax=96, eps_in=1e-3, rmax_in=48,
+                           red_in=1e-2, maxit_in=3000, maxit_out=30, check_every=5)
+        u, rep = P.solve(K, f, opts)
+        ud = T.full_vector(P.tt_to_cores(u))
+        err = np.linalg.norm(ud - uref) / np.linalg.norm(uref)
+        assert rep["status"] == 0 and err <= tol, (err, rep)
+
+
+def test_solve_warm_start_and_zero_load(P):
+    prob = W.cantilever_body_force(3)
+    K, f = P.assemble(prob)
+    opts = P.SolveOpts(tol=1e-10, eps=1e-12, rmax=64, eps_in=1e-3, rmax_in=32,
+                       maxit_in=2000, check_every=5)
+    u, rep = P.solve(K, f, opts)
+    # restarting from the converged solution costs no refinement step
+    u2, rep2 = P.solve(K, f, opts, x0=u)
+    assert rep2["outer"] == 0 and rep2["status"] == 0
+    # zero load gives the zero solution
+    z = P.tt_from_cores([np.zeros((1, c, 1)) for c in f.nrow])
+    u3, rep3 = P.solve(K, z, opts)
+    assert np.all(T.full_vector(P.tt_to_cores(u3)) == 0)
+
+
+def test_solve_reports_noconv(P):
+    prob = W.cantilever_body_force(4)
+    K, f = P.assemble(prob)
+    opts = P.SolveOpts(tol=1e-12, eps=1e-12, rmax=64, eps_in=1e-3, rmax_in=32,
+                       maxit_in=3, maxit_out=1, check_every=1)
+    u, rep = P.solve(K, f, opts)
+    assert rep["status"] == -4 and rep["outer"] == 1
