@@ -119,6 +119,22 @@ qtt_status qtt_assemble_stiffness(const qtt_problem *prob, double eps,
 qtt_status qtt_assemble_workspace(const qtt_problem *prob, size_t *bytes,
                                   int64_t *K_capacity, int64_t *f_capacity);
 
+/* qtt_assemble_bpx — additive multilevel (BPX) preconditioner for the
+ * stiffness of one square subdomain (q = 1), the tensor-structured
+ * preconditioning the paper points to for very fine grids (Sec. 1):
+ *   C = sum_{l=0}^{d} P_l P_l^T per displacement component,
+ * P_l interpolating level-l coarse nodal values (fine indices 2^l j, linear
+ * between coarse nodes, constant past the last one) onto the fine grid, the
+ * coarse node on a clamped end dropped (a clamp at the far end mirrors the
+ * construction), then C_bc = P C P + (1/gamma_D)(I - P) with the Dirichlet
+ * mask P and gamma_D of qtt_assemble_stiffness.  Each 1-D level has QTT rank
+ * <= 5 and C <= ~40 at any level.  C has K's modes; caller-provided data
+ * (capacity as K's from qtt_assemble_workspace), ranks written; same
+ * workspace as qtt_assemble_stiffness.  QTT_E_UNSUPPORTED for q > 1 or for
+ * clamps on both ends of one direction.  Synchronises `stream`.           */
+qtt_status qtt_assemble_bpx(const qtt_problem *prob, double eps, qtt_tt *C,
+                            void *ws, size_t ws_bytes, void *stream);
+
 /* qtt_matvec — y = A x core by core (strong Kronecker product, Sec. 4):
  *   y_k[(a,b), i, (c,d)] = sum_j A_k[a, i, j, c] x_k[b, j, d],
  * with the pair index (a,b) -> a r^x + b.  Output ranks are products of the
@@ -140,6 +156,18 @@ qtt_status qtt_matvec(const qtt_tt *A, const qtt_tt *x, qtt_tt *y,
 qtt_status qtt_round(qtt_tt *x, double eps, int32_t rmax, double *norm,
                      double *err, void *ws, size_t ws_bytes, void *stream);
 qtt_status qtt_round_workspace(const qtt_tt *x, int32_t rmax, size_t *bytes);
+
+/* qtt_round_sketch — randomised rounding in place for trains whose ranks are
+ * far above the result's (products such as K x): randomize-then-orthogonalize
+ * (Al Daas et al., SIAM J. Sci. Comput. 2023) with a Gaussian train of rank
+ * `ell` drawn from Philox4x32-10 keyed by `seed`, followed by qtt_round(eps,
+ * rmax) of the rank-<=ell result.  The error is close to the best rank-ell
+ * approximation's with high probability (not a deterministic bound).  *norm
+ * and *err are those of the final exact rounding.  Vectors only.
+ * Synchronises `stream`.                                                   */
+qtt_status qtt_round_sketch(qtt_tt *x, int32_t ell, uint64_t seed, double eps, int32_t rmax,
+                            double *norm, double *err, void *ws, size_t ws_bytes,
+                            void *stream);
 
 /* qtt_dot — <x, y> of two TT vectors of equal modes (left-to-right
  * environment sweep).  Synchronises `stream`.                              */
@@ -170,6 +198,9 @@ typedef struct {
                         products by a randomised sketch of this oversampling
                         before the exact rounding                            */
   uint64_t seed;     /* seed of the sketch generator (Philox4x32-10)         */
+  const qtt_tt *precond; /* NULL, or a QTT matrix C ~ K^-1 (symmetric positive
+                        definite, e.g. from qtt_assemble_bpx): the correction
+                        solve is then preconditioned CG with z = round(C r) */
 } qtt_solve_opts;
 
 typedef struct {

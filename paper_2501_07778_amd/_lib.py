@@ -50,7 +50,7 @@ class _SolveOpts(C.Structure):
                 ("eps_in", C.c_double), ("rmax_in", C.c_int32), ("red_in", C.c_double),
                 ("maxit_in", C.c_int32), ("maxit_out", C.c_int32),
                 ("check_every", C.c_int32), ("compute", C.c_int32),
-                ("sketch", C.c_int32), ("seed", C.c_uint64)]
+                ("sketch", C.c_int32), ("seed", C.c_uint64), ("precond", C.POINTER(_TT))]
 
 
 class _SolveReport(C.Structure):
@@ -79,15 +79,19 @@ def load_library(path: str = LIB_PATH):
     L.qtt_round.argtypes = [P(_TT), C.c_double, C.c_int32, P(C.c_double), P(C.c_double),
                             vp, sz, vp]
     L.qtt_round_workspace.argtypes = [P(_TT), C.c_int32, P(sz)]
+    L.qtt_round_sketch.argtypes = [P(_TT), C.c_int32, C.c_uint64, C.c_double, C.c_int32,
+                                   P(C.c_double), P(C.c_double), vp, sz, vp]
     L.qtt_dot.argtypes = [P(_TT), P(_TT), P(C.c_double), vp, sz, vp]
     L.qtt_axpby.argtypes = [C.c_double, P(_TT), C.c_double, P(_TT), P(_TT), vp, sz, vp]
     L.qtt_assemble_stiffness.argtypes = [P(_Problem), C.c_double, P(_TT), P(_TT), vp, sz, vp]
     L.qtt_assemble_workspace.argtypes = [P(_Problem), P(sz), P(C.c_int64), P(C.c_int64)]
+    L.qtt_assemble_bpx.argtypes = [P(_Problem), C.c_double, P(_TT), vp, sz, vp]
     L.qtt_solve.argtypes = [P(_TT), P(_TT), P(_TT), P(_SolveOpts), P(_TT), P(_SolveReport),
                             vp, sz, vp]
     L.qtt_solve_workspace.argtypes = [P(_TT), P(_TT), P(_SolveOpts), P(sz)]
-    for name in ("qtt_matvec", "qtt_round", "qtt_round_workspace", "qtt_dot", "qtt_axpby",
-                 "qtt_assemble_stiffness", "qtt_assemble_workspace", "qtt_solve",
+    for name in ("qtt_matvec", "qtt_round", "qtt_round_workspace", "qtt_round_sketch",
+                 "qtt_dot", "qtt_axpby",
+                 "qtt_assemble_stiffness", "qtt_assemble_workspace", "qtt_assemble_bpx", "qtt_solve",
                  "qtt_solve_workspace"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -227,6 +231,21 @@ def round_(x: TT, eps: float, rmax: int = 0):
     return nrm.value, err.value
 
 
+def round_sketch(x: TT, ell: int, seed: int, eps: float, rmax: int = 0):
+    """Randomised rounding in place (Gaussian sketch of rank ell, then the
+    exact rounding); returns (norm, discarded bound) of the exact step."""
+    need = C.c_size_t()
+    _check(lib().qtt_round_workspace(C.byref(x.c), int(rmax), C.byref(need)))
+    D = x.D
+    extra = 8 * (4 * max(x.ranks) * max(x.nrow) * ell * D + 8 * ell * ell * max(x.nrow) + 4 * max(x.ranks) * max(x.nrow) * ell * 4) + (1 << 20)
+    ws = _workspace(need.value + extra)
+    nrm, err = C.c_double(), C.c_double()
+    _check(lib().qtt_round_sketch(C.byref(x.c), int(ell), int(seed), float(eps), int(rmax),
+                                  C.byref(nrm), C.byref(err), C.c_void_p(_aligned_ptr(ws)),
+                                  ws.numel() - 256, _stream_ptr()))
+    return nrm.value, err.value
+
+
 def dot(x: TT, y: TT) -> float:
     caps = max(max(x.ranks) * max(y.ranks) * 3 * max(x.nrow), 1024)
     ws = _workspace(8 * caps + 8192)
@@ -298,6 +317,19 @@ def assemble(p, coupling: str = "symmetric", eps: float = 1e-14):
     return K, f
 
 
+def assemble_bpx(p, eps: float = 1e-14) -> TT:
+    """qtt_assemble_bpx: the BPX preconditioner of a single-square problem."""
+    prob = problem_from_workload(p)
+    wsb, kc, fc = C.c_size_t(), C.c_int64(), C.c_int64()
+    _check(lib().qtt_assemble_workspace(C.byref(prob.c), C.byref(wsb), C.byref(kc), C.byref(fc)))
+    modes = qtt_modes(p.level, len(p.subs))
+    Cm = TT(modes, modes, [1] * (len(modes) + 1), kc.value)
+    ws = _workspace(wsb.value)
+    _check(lib().qtt_assemble_bpx(C.byref(prob.c), float(eps), C.byref(Cm.c),
+                                  C.c_void_p(_aligned_ptr(ws)), ws.numel() - 256, _stream_ptr()))
+    return Cm
+
+
 # ---------------------------------------------------------------- solve
 @dataclass
 class SolveOpts:
@@ -313,11 +345,13 @@ class SolveOpts:
     compute: str = "f64"
     sketch: int = 0
     seed: int = 0
+    precond: Optional["TT"] = None
 
     def c(self) -> _SolveOpts:
+        pc = C.pointer(self.precond.c) if self.precond is not None else None
         return _SolveOpts(self.tol, self.eps, self.rmax, self.eps_in, self.rmax_in,
                           self.red_in, self.maxit_in, self.maxit_out, self.check_every,
-                          _DTYPES[self.compute], self.sketch, self.seed)
+                          _DTYPES[self.compute], self.sketch, self.seed, pc)
 
 
 def solve_workspace_bytes(K: TT, f: TT, opts: SolveOpts) -> int:

@@ -24,6 +24,8 @@ SOURCES = [
     "solve.cpp",
     "k_tt.hip",
     "k_round.hip",
+    "k_sketch.hip",
+    "k_full.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

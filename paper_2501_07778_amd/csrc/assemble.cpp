@@ -739,6 +739,148 @@ qtt_status check_problem(const qtt_problem *p) {
   return QTT_OK;
 }
 
+
+// ---------------------------------------------------------------- BPX
+// Linear function f(s) = c0 + sum_k ck 2^k s_k of the low l digits as a
+// rank-2 QTT "column" (row mode 2, column mode 1): the bond carries
+// (1, partial sum).
+HTT linear_low(int l, double c0, double slope) {
+  HTT t = HTT::make(l, true);
+  for (int k = 0; k < l; ++k) t.m[k] = 1;
+  for (int k = 0; k <= l; ++k) t.r[k] = (k == 0 || k == l) ? 1 : 2;
+  for (int k = 0; k < l; ++k) {
+    t.alloc(k);
+    const double ck = slope * std::ldexp(1.0, k);
+    for (int i = 0; i < 2; ++i) {
+      // 2x2 block [[1, ck i], [0, 1]] between the states (1, S)
+      double G[2][2] = {{1.0, ck * i}, {0.0, 1.0}};
+      if (k == 0) {
+        // start from the row (1, c0)
+        const double a0 = 1.0, a1 = c0;
+        const double v0 = a0 * G[0][0] + a1 * G[1][0];
+        const double v1 = a0 * G[0][1] + a1 * G[1][1];
+        if (l == 1) {
+          t.at(k, 0, i, 0, 0) = v1;
+        } else {
+          t.at(k, 0, i, 0, 0) = v0;
+          t.at(k, 0, i, 0, 1) = v1;
+        }
+      } else if (k == l - 1) {
+        // end by reading the sum: column (0, 1)
+        t.at(k, 0, i, 0, 0) = G[0][1];
+        t.at(k, 1, i, 0, 0) = G[1][1];
+      } else {
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b) t.at(k, a, i, 0, b) = G[a][b];
+      }
+    }
+  }
+  return t;
+}
+
+HTT concat(const HTT &lo, const HTT &hi) {
+  HTT t = lo;
+  t.D = lo.D + hi.D;
+  t.n.insert(t.n.end(), hi.n.begin(), hi.n.end());
+  t.m.insert(t.m.end(), hi.m.begin(), hi.m.end());
+  t.r.pop_back();
+  t.r.insert(t.r.end(), hi.r.begin(), hi.r.end());
+  t.c.insert(t.c.end(), hi.c.begin(), hi.c.end());
+  return t;
+}
+
+// B_l = P_l diag(m) P_l^T on 2^d points: P_l interpolates linearly between
+// the coarse nodes i = 2^l j and is constant past the last one; a clamp at
+// the low end drops coarse node 0 (m = 1 - e_0), a clamp at the high end
+// mirrors the construction (every digit flipped).
+HTT bpx_level_1d(int d, int l, bool clamp_lo, bool clamp_hi, Rounder &rd) {
+  HTT P;
+  const bool clamp = clamp_lo || clamp_hi;
+  if (l == 0) {
+    P = identity1(d);
+  } else if (l == d) {
+    if (clamp) return HTT();  // only the constant: removed by the clamp
+    P = HTT::make(d, true);
+    for (int k = 0; k < d; ++k) {
+      P.m[k] = 1;
+      P.alloc(k);
+      P.at(k, 0, 0, 0, 0) = P.at(k, 0, 1, 0, 0) = 1.0;
+    }
+  } else {
+    const double H = std::ldexp(1.0, l);
+    HTT a = linear_low(l, 1.0, -1.0 / H);
+    HTT b = linear_low(l, 0.0, 1.0 / H);
+    HTT I = identity1(d - l);
+    HTT J = shift1(d - l), El = outer1(d - l, 1, 1);
+    HTT S = add({&J, &El}, {1.0, 1.0});
+    HTT t1 = concat(a, I), t2 = concat(b, S);
+    P = add({&t1, &t2}, {1.0, 1.0});
+  }
+  HTT Pt = transpose(P);
+  HTT B;
+  if (clamp && l < d) {
+    // drop coarse node 0: P diag(1 - e_0) P^T
+    HTT mk = HTT::make(d, true);
+    for (int k = 0; k < d; ++k) {
+      const bool low = k < l;
+      mk.n[k] = mk.m[k] = low ? 1 : 2;
+      mk.alloc(k);
+      if (low) mk.at(k, 0, 0, 0, 0) = 1.0;
+      else mk.at(k, 0, 0, 0, 0) = mk.at(k, 0, 1, 1, 0) = 1.0;
+    }
+    HTT e0 = HTT::make(d, true);
+    for (int k = 0; k < d; ++k) {
+      const bool low = k < l;
+      e0.n[k] = e0.m[k] = low ? 1 : 2;
+      e0.alloc(k);
+      e0.at(k, 0, 0, 0, 0) = 1.0;
+    }
+    HTT m = add({&mk, &e0}, {1.0, -1.0});
+    if (l == 0) {
+      // level 0: P = I, the mask acts on the fine nodes directly
+      m = add({&mk, &e0}, {1.0, -1.0});
+    }
+    HTT Pm = matmat(P, m);
+    B = matmat(Pm, Pt);
+  } else {
+    B = matmat(P, Pt);
+  }
+  rd(B);
+  if (clamp_hi) {
+    for (int k = 0; k < B.D; ++k) {
+      std::vector<double> c = B.c[k];
+      for (int a = 0; a < B.r[k]; ++a)
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j)
+            for (int e = 0; e < B.r[k + 1]; ++e)
+              B.at(k, a, i, j, e) = c[a + (size_t)B.r[k] * ((1 - i) + 2 * ((1 - j) + 2 * (size_t)e))];
+    }
+  }
+  return B;
+}
+
+// node part of C for one component: sum_l B_l^y (z) B_l^x
+HTT bpx_nodes(int d, const uint8_t fixed[4][2], int c, Rounder &rd, bool &ok) {
+  const bool w = fixed[0][c], e = fixed[1][c], s = fixed[2][c], n = fixed[3][c];
+  ok = !(w && e) && !(s && n);
+  HTT acc;
+  bool have = false;
+  for (int l = 0; l <= d && ok; ++l) {
+    HTT bx = bpx_level_1d(d, l, w, e, rd);
+    HTT by = bpx_level_1d(d, l, s, n, rd);
+    if (bx.D == 0 || by.D == 0) continue;
+    HTT z = zkron(by, bx);
+    if (!have) {
+      acc = z;
+      have = true;
+    } else {
+      acc = add({&acc, &z}, {1.0, 1.0});
+    }
+    rd(acc);
+  }
+  return acc;
+}
+
 // bound on the rank of any intermediate before its rounding: products of
 // the copy-averaging operator with the block stiffness reach ~930 for three
 // subdomains; a single square stays below 256
@@ -841,6 +983,65 @@ extern "C" qtt_status qtt_assemble_stiffness(const qtt_problem *p, double eps, q
   };
   if ((st = put(Kbc, K, "K")) != QTT_OK) return st;
   if ((st = put(fbc, f, "f")) != QTT_OK) return st;
+  QTT_HIP(hipStreamSynchronize(rd.s));
+  return QTT_OK;
+}
+
+extern "C" qtt_status qtt_assemble_bpx(const qtt_problem *p, double eps, qtt_tt *C, void *ws,
+                                       size_t ws_bytes, void *stream) {
+  qtt_status st = check_problem(p);
+  if (st != QTT_OK) return st;
+  if (p->q != 1) return fail(QTT_E_UNSUPPORTED, "the BPX preconditioner is built for q = 1");
+  if (!C || !C->data || !C->ranks || !C->ncol) return fail(QTT_E_INVAL, "C has a NULL field");
+  const int D = 1 + 2 * p->level;
+  if (C->ncores != D) return fail(QTT_E_SHAPE, "C needs ncores = 1 + 2 level");
+  if (!ws) return fail(QTT_E_CAPACITY, "workspace is NULL");
+  Geometry g{p->level, 1, p};
+  Rounder rd;
+  rd.base.base = (char *)ws;
+  rd.base.size = ws_bytes;
+  rd.s = (hipStream_t)stream;
+  rd.eps = eps;
+  // gamma_D = trace(K)/N as in the assembly
+  HTT Kb = block_stiffness(g, rd);
+  if (rd.st != QTT_OK) return rd.st;
+  const double N = 2.0 * std::ldexp(1.0, 2 * p->level);
+  const double gD = trace(Kb) / N;
+  std::vector<HTT> comp;
+  for (int c = 0; c < 2; ++c) {
+    bool ok = true;
+    HTT node = bpx_nodes(p->level, p->sub[0].fixed, c, rd, ok);
+    if (!ok) return fail(QTT_E_UNSUPPORTED, "BPX needs at most one clamped end per direction");
+    if (rd.st != QTT_OK) return rd.st;
+    comp.push_back(with_prefix_matrix(g, sel_matrix(2, c, c), eye(1), node));
+  }
+  HTT Cm = add({&comp[0], &comp[1]}, {1.0, 1.0});
+  rd(Cm);
+  HTT mk = mask_vector(g, rd);
+  HTT Pm = diag_matrix(mk);
+  HTT one = ones_like(mk);
+  HTT cm = add({&one, &mk}, {1.0, -1.0});
+  rd(cm);
+  HTT Pc = diag_matrix(cm);
+  HTT PC = matmat(Pm, Cm);
+  rd(PC);
+  HTT PCP = matmat(PC, Pm);
+  rd(PCP);
+  HTT Cbc = add({&PCP, &Pc}, {1.0, 1.0 / gD});
+  rd(Cbc);
+  if (rd.st != QTT_OK) return rd.st;
+  for (int k = 0; k < D; ++k)
+    if (C->nrow[k] != Cbc.n[k] || C->ncol[k] != Cbc.m[k]) return fail(QTT_E_SHAPE, "C modes");
+  if (packed_size(Cbc) > C->capacity)
+    return fail(QTT_E_CAPACITY, "C: capacity " + std::to_string(C->capacity) + " < " +
+                                    std::to_string(packed_size(Cbc)));
+  int64_t off = 0;
+  for (int k = 0; k < D; ++k) {
+    QTT_HIP(hipMemcpyAsync(C->data + off, Cbc.c[k].data(), sizeof(double) * Cbc.c[k].size(),
+                           hipMemcpyHostToDevice, rd.s));
+    off += (int64_t)Cbc.c[k].size();
+  }
+  for (int k = 0; k <= D; ++k) C->ranks[k] = Cbc.r[k];
   QTT_HIP(hipStreamSynchronize(rd.s));
   return QTT_OK;
 }

@@ -227,6 +227,44 @@ qtt_status qtt_round(qtt_tt *x, double eps, int32_t rmax, double *norm,
   return QTT_OK;
 }
 
+qtt_status qtt_round_sketch(qtt_tt *x, int32_t ell, uint64_t seed, double eps, int32_t rmax,
+                            double *norm, double *err, void *ws, size_t ws_bytes,
+                            void *stream) {
+  qtt_status st;
+  if ((st = check_tt(x, "x", true)) != QTT_OK) return st;
+  if (x->ncol) return fail(QTT_E_INVAL, "x must be a vector");
+  if (ell < 1 || ell > 512) return fail(QTT_E_INVAL, "ell must be in 1..512");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(QTT_E_INVAL, "eps must be >= 0");
+  Arena ar;
+  ar.base = (char *)ws;
+  ar.size = ws_bytes;
+  TTDesc t;
+  std::vector<int> caps(x->ranks, x->ranks + x->ncores + 1);
+  arena_tt(ar, t, x->ncores, x->nrow, x->ncol, caps);
+  RoundWs w;
+  round_ws_take(ar, t.v, w);
+  double *sk = (double *)ar.take(sizeof(double) * sketch_ws_elems(t.v, ell));
+  if (!ws || !ar.ok())
+    return fail(QTT_E_CAPACITY, "workspace too small for qtt_round_sketch: need " +
+                                    std::to_string(ar.used));
+  hipStream_t s = (hipStream_t)stream;
+  QTT_HIP(upload_ranks(t.v, x->ranks, s));
+  QTT_HIP(launch_unpack(x->data, t.v, s));
+  QTT_HIP(sketch_tt(t.v, ell, seed, 0, sk, s));
+  QTT_HIP(round_tt(t.v, eps, rmax, w, s));
+  QTT_HIP(launch_pack(t.v, x->data, s));
+  int32_t rk_host[QTT_MAXD + 1];
+  double scal[2];
+  QTT_HIP(hipMemcpyAsync(rk_host, t.v.rk, sizeof(int32_t) * (x->ncores + 1),
+                         hipMemcpyDeviceToHost, s));
+  QTT_HIP(hipMemcpyAsync(scal, w.scal, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+  QTT_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k <= x->ncores; ++k) x->ranks[k] = rk_host[k];
+  if (norm) *norm = scal[0];
+  if (err) *err = std::sqrt(scal[1] > 0.0 ? scal[1] : 0.0);
+  return QTT_OK;
+}
+
 qtt_status qtt_dot(const qtt_tt *x, const qtt_tt *y, double *out, void *ws,
                    size_t ws_bytes, void *stream) {
   qtt_status st;

@@ -1,0 +1,83 @@
+// dev_gemm.h — FP64 GEMM tile shared by the kernels (device code only).
+// C = op(A) B for column-major operands: 64x64 output tile per 256-thread
+// block, K staged through LDS in steps of 16, 4x4 outputs per thread.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qtt {
+namespace dev {
+
+constexpr int GT = 64, GK = 16;
+
+template <bool TA>
+__device__ void gemm_tile(const double *A, int lda, const double *B, int ldb, double *C,
+                          int ldc, int M, int N, int K, int tm, int tn) {
+  __shared__ double As[GK][GT + 1];
+  __shared__ double Bs[GK][GT + 1];
+  const int tid = threadIdx.x;
+  const int tr = tid % 16, tc = tid / 16;
+  double acc[4][4] = {};
+  const int m0 = tm * GT, n0 = tn * GT;
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    for (int e = tid; e < GK * GT; e += 256) {
+      const int mm = e % GT, kk = e / GT;
+      const int gm = m0 + mm, gk = k0 + kk;
+      double av = 0.0;
+      if (gm < M && gk < K) av = TA ? A[gk + (int64_t)lda * gm] : A[gm + (int64_t)lda * gk];
+      As[kk][mm] = av;
+      const int kk2 = e % GK, nn = e / GK;
+      const int gk2 = k0 + kk2, gn = n0 + nn;
+      Bs[kk2][nn] = (gk2 < K && gn < N) ? B[gk2 + (int64_t)ldb * gn] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = As[kk][tr + 16 * u];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b[v] = Bs[kk][tc + 16 * v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gm = m0 + tr + 16 * u, gn = n0 + tc + 16 * v;
+      if (gm < M && gn < N) C[gm + (int64_t)ldc * gn] = acc[u][v];
+    }
+}
+
+// Split-K variant: block z handles the K range [z*kc, (z+1)*kc) and writes
+// its partial product to P + z*ldc*N (ldc = M); the partials are summed by
+// splitk_reduce.  Thin products (few output tiles, long K) need this to keep
+// enough blocks in flight.
+template <bool TA>
+__device__ void gemm_tile_k(const double *A, int lda, const double *B, int ldb, double *P,
+                            int M, int N, int K, int tm, int tn, int z, int kc) {
+  // every split takes at least kc; more when K needs more than gridDim.z splits
+  const int per = (K + (int)gridDim.z - 1) / (int)gridDim.z;
+  kc = per > kc ? per : kc;
+  const int k0 = z * kc;
+  const int kk = (K - k0) < kc ? (K - k0) : kc;
+  if (kk <= 0) {
+    // empty range: write zeros so the reduction stays uniform
+    for (int e = threadIdx.x; e < GT * GT; e += 256) {
+      const int gm = tm * GT + e % GT, gn = tn * GT + e / GT;
+      if (gm < M && gn < N) P[(int64_t)z * M * N + gm + (int64_t)M * gn] = 0.0;
+    }
+    return;
+  }
+  const double *Ak = TA ? A + k0 : A + (int64_t)lda * k0;
+  gemm_tile<TA>(Ak, lda, B + k0, ldb, P + (int64_t)z * M * N, M, M, N, kk, tm, tn);
+}
+
+}  // namespace dev
+}  // namespace qtt

@@ -119,6 +119,7 @@ enum ScalarOp {
 // rounding (exact algorithm); ws sized by round_workspace_elems
 struct RoundWs {
   double *carry, *rbuf, *work, *vbuf, *fold, *scal;  // scal: norm, err2
+  double *rotlog = nullptr;                           // Jacobi rotations
   int *iwork;
   int64_t carry_elems, sq_elems;
 };
@@ -129,6 +130,21 @@ bool round_ws_take(Arena &ar, const TTView &x, RoundWs &w);
 // eps by *eps_dev (device scalar).
 hipError_t round_tt(const TTView &x, double eps, int rmax, const RoundWs &w,
                     hipStream_t s);
+
+// randomised rounding of y to ranks <= ell (Gaussian sketch, seed/call
+// select the random numbers); ws holds sketch_ws_elems(y, ell) doubles
+int64_t sketch_ws_elems(const TTView &y, int ell);
+hipError_t sketch_tt(const TTView &y, int ell, uint64_t seed, uint64_t call, double *ws,
+                     hipStream_t s);
+
+// dense vector of a TT vector (first core least significant); host ranks
+// `rk` must equal the device ranks.  ws: full_ws_elems doubles.
+int64_t full_ws_elems(const TTView &v, const int32_t *rk);
+hipError_t tt_full(const TTView &v, const int32_t *rk, double *out, double *ws,
+                   hipStream_t s);
+// out[0] = sum_i (a_i - b_i)^2 over n entries, out[1] = sum_i a_i^2
+hipError_t launch_diff_norm2(const double *a, const double *b, int64_t n, double *out,
+                             hipStream_t s);
 
 // fills the device ranks from a host array
 hipError_t upload_ranks(const TTView &v, const int32_t *ranks,

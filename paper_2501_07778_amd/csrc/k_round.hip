@@ -24,6 +24,12 @@ namespace {
 constexpr int WG = 1024;           // threads of the one-workgroup kernels
 constexpr int NWAVE = WG / 64;
 constexpr int JACOBI_MAX_SWEEPS = 40;
+constexpr int GL = 32;             // lanes per column pair in the Jacobi sweeps
+constexpr int NGRP = WG / GL;
+// LDS-resident variants hold the whole working set of one step (matrix and
+// its second factor) in 150 KiB of LDS
+constexpr int LDS_DBL = 19200;
+constexpr int LDS_TAU = 160;       // min(rows, cols) <= sqrt(LDS_DBL)
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -140,25 +146,41 @@ __device__ void form_q(const double *W, int rows, int kq, const double *tau,
 }
 
 // Left sweep, core k: QR of the left unfolding (rows = nr[k]*nm_k,
-// cols = rk[k+1]); Q -> slot k, R -> rbuf (ld = r'), nr[k+1] = r'.
+// cols = rk[k+1]); Q -> slot k, R -> rbuf (ld = r'), nr[k+1] = r'.  The LDS
+// variant factors in LDS and forms Q there before writing it out.
+template <bool LDS>
 __global__ void __launch_bounds__(WG)
     k_qr_step(TTView x, int k, const double *src, double *work, double *rbuf,
-              double *tau, int *iwork) {
+              double *tau_g, int *iwork) {
   __shared__ double red[NWAVE];
+  __shared__ double lds[LDS ? LDS_DBL : 1];
+  __shared__ double tau_l[LDS ? LDS_TAU : 1];
   IW w = iw_of(iwork, x.D);
   const int nm = x.n[k] * x.m[k];
   const int rows = w.nr[k] * nm;
   const int cols = x.rk[k + 1];
   const int rq = rows < cols ? rows : cols;
-  for (int64_t e = threadIdx.x; e < (int64_t)rows * cols; e += WG) work[e] = src[e];
+  if (w.nr[k] > x.cap[k] || cols > x.cap[k + 1]) return;  // ranks beyond the slots
+  const bool use_lds = LDS && (int64_t)rows * cols <= LDS_DBL && rq <= LDS_TAU;
+  const bool q_lds = use_lds && (int64_t)rows * cols + (int64_t)rows * rq <= LDS_DBL;
+  double *W = use_lds ? lds : work;
+  double *tau = use_lds ? tau_l : tau_g;
+  for (int64_t e = threadIdx.x; e < (int64_t)rows * cols; e += WG) W[e] = src[e];
   __syncthreads();
-  householder_qr(work, rows, cols, tau, red);
+  householder_qr(W, rows, cols, tau, red);
   // R: rq x cols, upper trapezoid
   for (int64_t e = threadIdx.x; e < (int64_t)rq * cols; e += WG) {
     const int i = (int)(e % rq), c = (int)(e / rq);
-    rbuf[e] = (i <= c) ? work[i + (int64_t)rows * c] : 0.0;
+    rbuf[e] = (i <= c) ? W[i + (int64_t)rows * c] : 0.0;
   }
-  form_q(work, rows, rq, tau, x.data + x.off[k]);
+  double *slot = x.data + x.off[k];
+  if (q_lds) {
+    double *Q = lds + (int64_t)rows * cols;
+    form_q(W, rows, rq, tau, Q);
+    for (int64_t e = threadIdx.x; e < (int64_t)rows * rq; e += WG) slot[e] = Q[e];
+  } else {
+    form_q(W, rows, rq, tau, slot);
+  }
   if (threadIdx.x == 0) w.nr[k + 1] = rq;
 }
 
@@ -214,6 +236,7 @@ __global__ void __launch_bounds__(256)
   const int M = w.nr[k + 1];
   const int K = x.rk[k + 1];
   const int N = x.n[k + 1] * x.m[k + 1] * x.rk[k + 2];
+  if (M > x.cap[k + 1] || K > x.cap[k + 1] || x.rk[k + 2] > x.cap[k + 2]) return;
   if (blockIdx.x * GT >= M || blockIdx.y * GT >= N) return;
   gemm_tile(rbuf, M, x.data + x.off[k + 1], K, carry, M, M, N, K, blockIdx.x,
             blockIdx.y);
@@ -227,6 +250,7 @@ __global__ void __launch_bounds__(256)
   const int M = w.nr[k - 1] * x.n[k - 1] * x.m[k - 1];
   const int K = w.nr[k];
   const int N = w.fr[k];
+  if (w.nr[k - 1] > x.cap[k - 1] || K > x.cap[k] || N > x.cap[k]) return;
   if (blockIdx.x * GT >= M || blockIdx.y * GT >= N) return;
   gemm_tile(x.data + x.off[k - 1], M, F, K, carry, M, M, N, K, blockIdx.x,
             blockIdx.y);
@@ -245,113 +269,153 @@ __global__ void __launch_bounds__(WG)
   if (threadIdx.x == 0) scal[0] = sqrt(p);
 }
 
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = GL / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GL);
+  return v;
+}
+
 // One-sided Jacobi (Hestenes) on the columns of B (mb x nb, ld = mb) with V
 // (nb x nb) accumulated: B V has mutually orthogonal columns.  Round-robin
-// ordering: each round pairs all columns disjointly, one wave per pair.
-__device__ void jacobi(double *B, int mb, int nb, double *V, int *flag) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int64_t e = threadIdx.x; e < (int64_t)nb * nb; e += WG)
-    V[e] = ((e % nb) == (e / nb)) ? 1.0 : 0.0;
+// ordering: each round pairs all columns disjointly, one 32-lane group per
+// pair.  A pair is rotated while |b_p . b_q| > tol ||b_p|| ||b_q||; since V
+// stays orthogonal, B_in = (B V) V^T holds whatever tol is, and columns
+// dropped later contribute exactly their norms to the truncation error.
+__device__ int jacobi(double *B, int mb, int nb, double *V, double *rot_log, int *flag,
+                      double tol) {
+  const int gl = threadIdx.x % GL, grp = threadIdx.x / GL;
+  if (V)
+    for (int64_t e = threadIdx.x; e < (int64_t)nb * nb; e += WG)
+      V[e] = ((e % nb) == (e / nb)) ? 1.0 : 0.0;
   const int N = nb + (nb & 1);
-  const double tol = 1e-15 * sqrt((double)mb);
+  int sweeps = 0;
   for (int sweep = 0; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
     __syncthreads();
     if (threadIdx.x == 0) *flag = 0;
     __syncthreads();
     for (int r = 0; r < N - 1; ++r) {
-      for (int i = wave; i < N / 2; i += NWAVE) {
+      double *lg = rot_log ? rot_log + 2 * ((int64_t)(sweep * (N - 1) + r) * (N / 2)) : nullptr;
+      for (int i = grp; i < N / 2; i += NGRP) {
         int p = (r + i) % (N - 1);
         int q = (i == 0) ? (N - 1) : (r - i + N - 1) % (N - 1);
-        if (p >= nb || q >= nb) continue;
-        if (p > q) { int t = p; p = q; q = t; }
-        double *bp = B + (int64_t)mb * p, *bq = B + (int64_t)mb * q;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int l = lane; l < mb; l += 64) {
-          const double u = bp[l], v = bq[l];
-          al = fma(u, u, al);
-          be = fma(v, v, be);
-          ga = fma(u, v, ga);
+        double c = 1.0, sn = 0.0;
+        if (p < nb && q < nb) {
+          if (p > q) { int t = p; p = q; q = t; }
+          double *bp = B + (int64_t)mb * p, *bq = B + (int64_t)mb * q;
+          double al = 0.0, be = 0.0, ga = 0.0;
+          for (int l = gl; l < mb; l += GL) {
+            const double u = bp[l], v = bq[l];
+            al = fma(u, u, al);
+            be = fma(v, v, be);
+            ga = fma(u, v, ga);
+          }
+          al = group_sum(al);
+          be = group_sum(be);
+          ga = group_sum(ga);
+          if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+            const double zeta = (be - al) / (2.0 * ga);
+            double t;
+            if (fabs(zeta) > 1e150)
+              t = 0.5 / zeta;
+            else
+              t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = c * t;
+            for (int l = gl; l < mb; l += GL) {
+              const double u = bp[l], v = bq[l];
+              bp[l] = c * u - sn * v;
+              bq[l] = sn * u + c * v;
+            }
+            if (V) {
+              double *vp = V + (int64_t)nb * p, *vq = V + (int64_t)nb * q;
+              for (int l = gl; l < nb; l += GL) {
+                const double u = vp[l], v = vq[l];
+                vp[l] = c * u - sn * v;
+                vq[l] = sn * u + c * v;
+              }
+            }
+            if (gl == 0) *flag = 1;
+          }
         }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al * be))) continue;
-        const double zeta = (be - al) / (2.0 * ga);
-        double t;
-        if (fabs(zeta) > 1e150)
-          t = 0.5 / zeta;
-        else
-          t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        for (int l = lane; l < mb; l += 64) {
-          const double u = bp[l], v = bq[l];
-          bp[l] = c * u - s * v;
-          bq[l] = s * u + c * v;
+        if (lg && gl == 0) {
+          lg[2 * i] = c;
+          lg[2 * i + 1] = sn;
         }
-        double *vp = V + (int64_t)nb * p, *vq = V + (int64_t)nb * q;
-        for (int l = lane; l < nb; l += 64) {
-          const double u = vp[l], v = vq[l];
-          vp[l] = c * u - s * v;
-          vq[l] = s * u + c * v;
-        }
-        if (lane == 0) *flag = 1;
       }
       __syncthreads();
     }
+    sweeps = sweep + 1;
     __syncthreads();
     if (*flag == 0) break;
   }
   __syncthreads();
+  return sweeps;
 }
 
-// Right sweep, core k: SVD of the right unfolding M (r0 = nr[k] rows,
-// nc = nm_k * fr[k+1] columns) held in `carry`; writes V^T-type factor to
-// slot k, the fold operand F (r0 x rank) and fr[k] = rank.
-__global__ void __launch_bounds__(WG)
-    k_svd_step(TTView x, int k, double eps, int rmax, const double *carry,
-               double *work, double *vbuf, double *F, double *sig,
-               int *iwork, double *scal) {
-  __shared__ double red[NWAVE];
-  __shared__ int flag;
-  __shared__ int rank_s;
-  IW w = iw_of(iwork, x.D);
-  const int D = x.D;
-  const int nm = x.n[k] * x.m[k];
-  const int r0 = w.nr[k];
-  const int nc = nm * w.fr[k + 1];
-  const bool tall = r0 >= nc;
-  const int mb = tall ? r0 : nc, nb = tall ? nc : r0;
-  // B = M (tall) or M^T (wide), column-major mb x nb
-  for (int64_t e = threadIdx.x; e < (int64_t)mb * nb; e += WG) {
-    const int i = (int)(e % mb), j = (int)(e / mb);
-    work[e] = tall ? carry[e] : carry[j + (int64_t)r0 * i];
+// V (nb x nb) = product of the logged rotations, replayed in the order of
+// the sweeps: identical to accumulating them during the sweeps.
+__device__ void jacobi_replay(double *V, int nb, const double *rot_log, int sweeps) {
+  const int gl = threadIdx.x % GL, grp = threadIdx.x / GL;
+  for (int64_t e = threadIdx.x; e < (int64_t)nb * nb; e += WG)
+    V[e] = ((e % nb) == (e / nb)) ? 1.0 : 0.0;
+  const int N = nb + (nb & 1);
+  __syncthreads();
+  for (int sweep = 0; sweep < sweeps; ++sweep) {
+    for (int r = 0; r < N - 1; ++r) {
+      const double *lg = rot_log + 2 * ((int64_t)(sweep * (N - 1) + r) * (N / 2));
+      for (int i = grp; i < N / 2; i += NGRP) {
+        int p = (r + i) % (N - 1);
+        int q = (i == 0) ? (N - 1) : (r - i + N - 1) % (N - 1);
+        if (p >= nb || q >= nb) continue;
+        if (p > q) { int t = p; p = q; q = t; }
+        const double c = lg[2 * i], sn = lg[2 * i + 1];
+        if (sn == 0.0 && c == 1.0) continue;
+        double *vp = V + (int64_t)nb * p, *vq = V + (int64_t)nb * q;
+        for (int l = gl; l < nb; l += GL) {
+          const double u = vp[l], v = vq[l];
+          vp[l] = c * u - sn * v;
+          vq[l] = sn * u + c * v;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__device__ __forceinline__ double jacobi_tol(double eps, int mb) {
+  const double floor = 1e-15 * sqrt((double)mb);
+  const double t = fmin(1e-2 * eps, 1e-6);
+  return t > floor ? t : floor;
+}
+
+// Truncation after the Jacobi sweeps: sigma_j = ||(B V)_j||, descending
+// order by parallel ranking, smallest rank with discarded tail <= delta,
+// capped at rmax.  Shared by the LDS and global variants.
+__device__ int truncate_rank(const double *Bv, int mb, int nb, double *sig, int *perm,
+                             double delta, int rmax, double *scal, int *rank_s) {
+  for (int j = threadIdx.x / 64; j < nb; j += NWAVE) {
+    const double *bj = Bv + (int64_t)mb * j;
+    double sacc = 0.0;
+    for (int l = threadIdx.x & 63; l < mb; l += 64) sacc = fma(bj[l], bj[l], sacc);
+    sacc = wave_sum(sacc);
+    if ((threadIdx.x & 63) == 0) sig[j] = sqrt(sacc);
   }
   __syncthreads();
-  jacobi(work, mb, nb, vbuf, &flag);
-  // column norms
-  for (int j = threadIdx.x >> 6; j < nb; j += NWAVE) {
-    const double *bj = work + (int64_t)mb * j;
-    double s = 0.0;
-    for (int l = threadIdx.x & 63; l < mb; l += 64) s = fma(bj[l], bj[l], s);
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) sig[j] = sqrt(s);
+  for (int j = threadIdx.x; j < nb; j += WG) {
+    const double sj = sig[j];
+    int pos = 0;
+    for (int i = 0; i < nb; ++i) {
+      const double si = sig[i];
+      pos += (si > sj || (si == sj && i < j)) ? 1 : 0;
+    }
+    perm[pos] = j;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    // descending order by selection (nb is at most a few hundred)
-    for (int j = 0; j < nb; ++j) w.perm[j] = j;
-    for (int a = 0; a < nb; ++a) {
-      int best = a;
-      for (int b = a + 1; b < nb; ++b)
-        if (sig[w.perm[b]] > sig[w.perm[best]]) best = b;
-      int t = w.perm[a]; w.perm[a] = w.perm[best]; w.perm[best] = t;
-    }
-    const double delta = (D > 1) ? eps * scal[0] / sqrt((double)(D - 1)) : 0.0;
-    // smallest rank with tail <= delta
     double tail2 = 0.0;
     int rank = nb;
     for (int j = nb - 1; j >= 0; --j) {
-      const double sj = sig[w.perm[j]];
+      const double sj = sig[perm[j]];
       if (sqrt(tail2 + sj * sj) <= delta) {
         tail2 += sj * sj;
         rank = j;
@@ -362,35 +426,112 @@ __global__ void __launch_bounds__(WG)
     if (rank < 1) rank = 1;
     if (rmax > 0 && rank > rmax) rank = rmax;
     double disc = 0.0;
-    for (int j = rank; j < nb; ++j) disc += sig[w.perm[j]] * sig[w.perm[j]];
+    for (int j = rank; j < nb; ++j) disc += sig[perm[j]] * sig[perm[j]];
     scal[1] += disc;
-    w.fr[k] = rank;
-    rank_s = rank;
+    *rank_s = rank;
   }
   __syncthreads();
-  const int rank = rank_s;
-  double *core = x.data + x.off[k];  // rank x nc
+  return *rank_s;
+}
+
+// Write the new right-orthogonal core and the fold operand from B V = W
+// (tall: B = M) or B = M^T (wide).
+__device__ void svd_outputs(bool tall, const double *Wb, const double *V, int mb, int nb,
+                            int r0, int nc, int rank, const double *sig, const int *perm,
+                            double *core, double *F) {
   if (tall) {
-    // M V = W: F = W[:, perm[:rank]] (r0 x rank), core = V[:, perm]^T
     for (int64_t e = threadIdx.x; e < (int64_t)r0 * rank; e += WG) {
       const int a = (int)(e % r0), l = (int)(e / r0);
-      F[e] = work[a + (int64_t)mb * w.perm[l]];
+      F[e] = Wb[a + (int64_t)mb * perm[l]];
     }
     for (int64_t e = threadIdx.x; e < (int64_t)rank * nc; e += WG) {
       const int l = (int)(e % rank), col = (int)(e / rank);
-      core[e] = vbuf[col + (int64_t)nb * w.perm[l]];
+      core[e] = V[col + (int64_t)nb * perm[l]];
     }
   } else {
-    // M^T V = W: M = V W^T; F = V[:, perm] * sigma, core = (W / sigma)^T
     for (int64_t e = threadIdx.x; e < (int64_t)r0 * rank; e += WG) {
       const int a = (int)(e % r0), l = (int)(e / r0);
-      F[e] = vbuf[a + (int64_t)nb * w.perm[l]] * sig[w.perm[l]];
+      F[e] = V[a + (int64_t)nb * perm[l]] * sig[perm[l]];
     }
     for (int64_t e = threadIdx.x; e < (int64_t)rank * nc; e += WG) {
       const int l = (int)(e % rank), col = (int)(e / rank);
-      const double s = sig[w.perm[l]];
-      core[e] = (s > 0.0) ? work[col + (int64_t)mb * w.perm[l]] / s
-                          : ((col == l) ? 1.0 : 0.0);
+      const double sv = sig[perm[l]];
+      core[e] = (sv > 0.0) ? Wb[col + (int64_t)mb * perm[l]] / sv : ((col == l) ? 1.0 : 0.0);
+    }
+  }
+}
+
+// Right sweep, core k: SVD of the right unfolding M (r0 = nr[k] rows,
+// nc = nm_k * fr[k+1] columns) held in `carry`; writes the right-orthogonal
+// core to slot k, the fold operand F (r0 x rank) and fr[k] = rank.  The LDS
+// variant keeps B and V in LDS (the host picks it when the caps fit).
+template <bool LDS>
+__global__ void __launch_bounds__(WG)
+    k_svd_step(TTView x, int k, double eps, int rmax, const double *carry,
+               double *work, double *vbuf, double *F, double *sig,
+               int *iwork, double *scal, double *rot_log) {
+  __shared__ int flag;
+  __shared__ int rank_s;
+  __shared__ double lds[LDS ? LDS_DBL : 1];
+  IW w = iw_of(iwork, x.D);
+  const int D = x.D;
+  const int nm = x.n[k] * x.m[k];
+  const int r0 = w.nr[k];
+  const int nc = nm * w.fr[k + 1];
+  const bool tall = r0 >= nc;
+  const int mb = tall ? r0 : nc, nb = tall ? nc : r0;
+  if (r0 > x.cap[k] || w.fr[k + 1] > x.cap[k + 1]) return;  // ranks beyond the slots
+  // B and V both in LDS, or B in LDS with the rotations logged and replayed
+  // onto V in the same LDS afterwards, or both in global memory
+  const bool both = LDS && (int64_t)mb * nb + (int64_t)nb * nb <= LDS_DBL;
+  const bool replay = LDS && !both && (int64_t)mb * nb <= LDS_DBL &&
+                      (int64_t)nb * nb <= LDS_DBL;
+  double *B = (both || replay) ? lds : work;
+  double *V = both ? lds + (int64_t)mb * nb : (replay ? nullptr : vbuf);
+  // B = M (tall) or M^T (wide), column-major mb x nb
+  for (int64_t e = threadIdx.x; e < (int64_t)mb * nb; e += WG) {
+    const int i = (int)(e % mb), j = (int)(e / mb);
+    B[e] = tall ? carry[e] : carry[j + (int64_t)r0 * i];
+  }
+  __syncthreads();
+  // tall: the kept core is V^T, orthogonal for any stopping tolerance; wide:
+  // it is built from the columns of B V, which must be orthogonal to FP64
+  const int sweeps = jacobi(B, mb, nb, V, replay ? rot_log : nullptr, &flag,
+                            jacobi_tol(tall ? eps : 0.0, mb));
+  const double delta = (D > 1) ? eps * scal[0] / sqrt((double)(D - 1)) : 0.0;
+  const int rank = truncate_rank(B, mb, nb, sig, w.perm, delta, rmax, scal, &rank_s);
+  if (threadIdx.x == 0) w.fr[k] = rank;
+  double *core = x.data + x.off[k];
+  if (!replay) {
+    svd_outputs(tall, B, V, mb, nb, r0, nc, rank, sig, w.perm, core, F);
+    return;
+  }
+  // outputs that need B, then V replayed into the LDS B occupied
+  if (tall) {
+    for (int64_t e = threadIdx.x; e < (int64_t)r0 * rank; e += WG) {
+      const int a = (int)(e % r0), l = (int)(e / r0);
+      F[e] = B[a + (int64_t)mb * w.perm[l]];
+    }
+  } else {
+    for (int64_t e = threadIdx.x; e < (int64_t)rank * nc; e += WG) {
+      const int l = (int)(e % rank), col = (int)(e / rank);
+      const double sv = sig[w.perm[l]];
+      core[e] = (sv > 0.0) ? B[col + (int64_t)mb * w.perm[l]] / sv : ((col == l) ? 1.0 : 0.0);
+    }
+  }
+  __syncthreads();
+  jacobi_replay(lds, nb, rot_log, sweeps);
+  __syncthreads();
+  const double *Vl = lds;
+  if (tall) {
+    for (int64_t e = threadIdx.x; e < (int64_t)rank * nc; e += WG) {
+      const int l = (int)(e % rank), col = (int)(e / rank);
+      core[e] = Vl[col + (int64_t)nb * w.perm[l]];
+    }
+  } else {
+    for (int64_t e = threadIdx.x; e < (int64_t)r0 * rank; e += WG) {
+      const int a = (int)(e % r0), l = (int)(e / r0);
+      F[e] = Vl[a + (int64_t)nb * w.perm[l]] * sig[w.perm[l]];
     }
   }
 }
@@ -398,6 +539,7 @@ __global__ void __launch_bounds__(WG)
 // slot 0 <- carry (1 x nm_0 x fr[1]), ranks <- fr
 __global__ void k_round_finish(TTView x, const double *carry, int *iwork) {
   IW w = iw_of(iwork, x.D);
+  if (w.fr[1] > x.cap[1]) return;
   const int64_t ne = (int64_t)x.n[0] * x.m[0] * w.fr[1];
   double *core = x.data + x.off[0];
   for (int64_t e = threadIdx.x; e < ne; e += blockDim.x) core[e] = carry[e];
@@ -464,6 +606,10 @@ bool round_ws_take(Arena &ar, const TTView &x, RoundWs &w) {
   w.fold = (double *)ar.take(sizeof(double) * cap * cap * nm);
   w.scal = (double *)ar.take(sizeof(double) * (4 + 2 * nm * cap));
   w.iwork = (int *)ar.take(sizeof(int) * (2 * (x.D + 1) + nm * cap + 8));
+  // Jacobi rotation log: (c, s) for every pair of every round of every sweep
+  // for matrices up to the LDS size (nb <= 138 columns)
+  const int64_t nbl = 140;
+  w.rotlog = (double *)ar.take(sizeof(double) * 2 * JACOBI_MAX_SWEEPS * nbl * (nbl / 2));
   return ar.ok();
 }
 
@@ -481,8 +627,14 @@ hipError_t round_tt(const TTView &x, double eps, int rmax, const RoundWs &w,
   hipLaunchKernelGGL(k_round_init, dim3(1), dim3(64), 0, s, x, w.iwork, w.scal);
   for (int k = 0; k < D - 1; ++k) {
     const double *src = (k == 0) ? x.data + x.off[0] : w.carry;
-    hipLaunchKernelGGL(k_qr_step, dim3(1), dim3(WG), 0, s, x, k, src, w.work,
-                       w.rbuf, tau, w.iwork);
+    const int64_t rc = (int64_t)x.cap[k] * x.n[k] * x.m[k];
+    const int64_t cc = x.cap[k + 1];
+    if (rc * cc <= LDS_DBL && (rc < cc ? rc : cc) <= LDS_TAU)
+      hipLaunchKernelGGL(k_qr_step<true>, dim3(1), dim3(WG), 0, s, x, k, src, w.work,
+                         w.rbuf, tau, w.iwork);
+    else
+      hipLaunchKernelGGL(k_qr_step<false>, dim3(1), dim3(WG), 0, s, x, k, src, w.work,
+                         w.rbuf, tau, w.iwork);
     const int mt = (x.cap[k + 1] + GT - 1) / GT;
     const int nt = (x.n[k + 1] * x.m[k + 1] * x.cap[k + 2] + GT - 1) / GT;
     hipLaunchKernelGGL(k_absorb, dim3(mt, nt), dim3(256), 0, s, x, k, w.rbuf,
@@ -491,8 +643,18 @@ hipError_t round_tt(const TTView &x, double eps, int rmax, const RoundWs &w,
   hipLaunchKernelGGL(k_last_norm, dim3(1), dim3(WG), 0, s, x, w.carry, w.iwork,
                      w.scal);
   for (int k = D - 1; k >= 1; --k) {
-    hipLaunchKernelGGL(k_svd_step, dim3(1), dim3(WG), 0, s, x, k, eps, rmax,
-                       w.carry, w.work, w.vbuf, w.fold, sig, w.iwork, w.scal);
+    // fr[k+1] <= min(cap, rmax): the truncation already happened to its right
+    const int64_t frc = (rmax > 0 && rmax < x.cap[k + 1]) ? rmax : x.cap[k + 1];
+    const int64_t r0c = x.cap[k];
+    const int64_t ncc = (int64_t)x.n[k] * x.m[k] * frc;
+    const int64_t nbc = r0c < ncc ? r0c : ncc;
+    const int64_t mbc = r0c > ncc ? r0c : ncc;
+    if (mbc * nbc <= LDS_DBL && nbc * nbc <= LDS_DBL)
+      hipLaunchKernelGGL(k_svd_step<true>, dim3(1), dim3(WG), 0, s, x, k, eps, rmax,
+                         w.carry, w.work, w.vbuf, w.fold, sig, w.iwork, w.scal, w.rotlog);
+    else
+      hipLaunchKernelGGL(k_svd_step<false>, dim3(1), dim3(WG), 0, s, x, k, eps, rmax,
+                         w.carry, w.work, w.vbuf, w.fold, sig, w.iwork, w.scal, w.rotlog);
     const int mt = (x.cap[k - 1] * x.n[k - 1] * x.m[k - 1] + GT - 1) / GT;
     const int nt = (x.cap[k] + GT - 1) / GT;
     hipLaunchKernelGGL(k_fold, dim3(mt, nt), dim3(256), 0, s, x, k, w.fold,

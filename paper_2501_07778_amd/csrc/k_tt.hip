@@ -42,6 +42,8 @@ __global__ void __launch_bounds__(MV_TX *MV_TY)
   const int n = A.n[k], m = A.m[k];
   const int P = ra0 * rx0;
   const int ncols = n * ra1 * rx1;
+  // never write past the output slot (its caps bound the product ranks)
+  if (P > y.cap[k] || ra1 * rx1 > y.cap[k + 1]) return;
   const double *Ak = A.data + A.off[k];
   const double *xk = x.data + x.off[k];
   double *yk = y.data + y.off[k];
@@ -83,6 +85,8 @@ __global__ void __launch_bounds__(MV_TX *MV_TY)
   const int n = A.n[k], m = A.m[k];
   const int P = ra0 * rx0;
   const int ncols = n * ra1 * rx1;
+  // never write past the output slot (its caps bound the product ranks)
+  if (P > y.cap[k] || ra1 * rx1 > y.cap[k + 1]) return;
   const double *Ak = A.data + A.off[k];
   const double *xk = x.data + x.off[k];
   double *yk = y.data + y.off[k];
@@ -122,6 +126,7 @@ __device__ __forceinline__ int64_t core_elems(const int *rk, const TTView &v,
 // packed <-> slotted: block y = core, grid-stride over elements
 __global__ void k_pack(TTView v, double *packed, int to_packed) {
   const int k = blockIdx.y;
+  if (v.rk[k] > v.cap[k] || v.rk[k + 1] > v.cap[k + 1]) return;
   int64_t off = 0;
   for (int l = 0; l < k; ++l) off += core_elems(v.rk, v, l);
   const int64_t ne = core_elems(v.rk, v, k);
@@ -140,6 +145,7 @@ __global__ void k_copy_tt(TTView a, TTView b) {
   const int k = blockIdx.y;
   if (blockIdx.x == 0 && k == 0 && threadIdx.x <= a.D)
     b.rk[threadIdx.x] = a.rk[threadIdx.x];
+  if (a.rk[k] > b.cap[k] || a.rk[k + 1] > b.cap[k + 1]) return;
   const int64_t ne = core_elems(a.rk, a, k);
   const double *src = a.data + a.off[k];
   double *dst = b.data + b.off[k];
@@ -165,6 +171,7 @@ __global__ void k_axpby(double a, const double *a_dev, TTView x, double b,
   const int nm = x.n[k] * x.m[k];
   const int rz0 = (k == 0) ? 1 : rx0 + ry0;
   const int rz1 = (k == D - 1) ? 1 : rx1 + ry1;
+  if (rz0 > z.cap[k] || rz1 > z.cap[k + 1]) return;
   const int64_t ne = (int64_t)rz0 * nm * rz1;
   const double *xk = x.data + x.off[k];
   const double *yk = y.data + y.off[k];

@@ -8,13 +8,23 @@
 //   outer (FP64):  r = round(f - K u); stop when ||f - K u|| <= tol ||f||
 //                  (the norm of the unrounded difference comes out of the
 //                  rounding's QR sweep); e = CG(K, r); u = round(u + e)
-//   inner:         CG with every iterate, residual, direction and product
-//                  K p rounded to (eps_in, rmax_in); ||r||^2 is read off the
-//                  rounding of r (norm^2 minus the discarded sigma^2).
+//   inner:         truncated CG: the products K p and C r are formed
+//                  exactly and used unrounded in <p, K p> and <r, C r>; the
+//                  new residual r - alpha K p and direction z + beta p are
+//                  rounded as sums to (eps_in, rmax_in), so each truncation
+//                  error is relative to the vector CG continues with; the
+//                  iterate is rounded to (eps, rmax) (its truncation error
+//                  reaches the true residual multiplied by ||K||); ||r||^2 is
+//                  read off the rounding of r.  With a preconditioner C
+//                  (QTT matrix ~ K^-1) z = C r, otherwise z = r.
 // All scalars and ranks stay on the device; the host synchronises only at
 // the convergence checks (every check_every inner iterations and once per
 // refinement step).
+#include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <utility>
@@ -31,6 +41,10 @@ struct SolveLayout {
   double *dot_ws = nullptr;
   int64_t dot_elems = 0;
   double *sc = nullptr;  // device scalars
+  double *sk_ws = nullptr;    // randomised rounding
+  double *dense = nullptr;    // dense residual (N doubles)
+  double *full_ws = nullptr;  // dense contraction workspace
+  int64_t N = 0;
 };
 
 enum {
@@ -56,6 +70,16 @@ bool carve(Arena &ar, const qtt_tt *K, const qtt_tt *f, const qtt_solve_opts *o,
     for (int k = 0; k <= D; ++k) c[k] *= K->ranks[k];
     return c;
   };
+  // products with the preconditioner share the buffer of K p
+  auto op_caps = [&](int r) {
+    std::vector<int> c = caps_for(K, r);
+    for (int k = 0; k <= D; ++k) {
+      int R = K->ranks[k];
+      if (o->precond) R = R > o->precond->ranks[k] ? R : o->precond->ranks[k];
+      c[k] *= R;
+    }
+    return c;
+  };
   auto sum_caps = [&](std::vector<int> a, const std::vector<int> &b) {
     for (size_t k = 0; k < a.size(); ++k) a[k] += b[k];
     a.front() = a.back() = 1;
@@ -64,17 +88,19 @@ bool carve(Arena &ar, const qtt_tt *K, const qtt_tt *f, const qtt_solve_opts *o,
   std::vector<int> cu = caps_for(K, rmax), ci = caps_for(K, rin);
   std::vector<int> cf(f->ranks, f->ranks + D + 1);
   bool ok = true;
-  for (int s = 0; s < 2; ++s) ok &= arena_tt(ar, L.U[s], D, n, nullptr, sum_caps(cu, ci));
+  // u + e: both ranks are bounded by rmax (the correction keeps the outer
+  // accuracy)
+  for (int s = 0; s < 2; ++s) ok &= arena_tt(ar, L.U[s], D, n, nullptr, sum_caps(cu, cu));
   ok &= arena_tt(ar, L.Ku, D, n, nullptr, prod_caps(rmax));
   std::vector<int> cr = sum_caps(prod_caps(rmax), cf);
   ok &= arena_tt(ar, L.R, D, n, nullptr, sum_caps(cr, ci));
   std::vector<int> c2 = sum_caps(sum_caps(ci, ci), ci);
   for (int s = 0; s < 2; ++s) {
-    ok &= arena_tt(ar, L.X[s], D, n, nullptr, c2);
-    ok &= arena_tt(ar, L.Rr[s], D, n, nullptr, sum_caps(ci, prod_caps(rin)));
-    ok &= arena_tt(ar, L.Pp[s], D, n, nullptr, c2);
+    ok &= arena_tt(ar, L.X[s], D, n, nullptr, sum_caps(sum_caps(cu, ci), ci));
+    ok &= arena_tt(ar, L.Rr[s], D, n, nullptr, sum_caps(ci, op_caps(rin)));
+    ok &= arena_tt(ar, L.Pp[s], D, n, nullptr, sum_caps(ci, op_caps(rin)));
   }
-  ok &= arena_tt(ar, L.Q, D, n, nullptr, prod_caps(rin));
+  ok &= arena_tt(ar, L.Q, D, n, nullptr, op_caps(rin));
   // the rounding workspace serves every operand: size it for the bondwise
   // largest caps
   TTView big = L.R.v;
@@ -84,10 +110,24 @@ bool carve(Arena &ar, const qtt_tt *K, const qtt_tt *f, const qtt_solve_opts *o,
   TTView fv = L.R.v;
   for (int k = 0; k <= D; ++k) fv.cap[k] = cf[k];
   L.dot_elems = dot_ws_elems(L.R.v, L.R.v);
-  for (int64_t e : {dot_ws_elems(fv, fv), dot_ws_elems(L.Pp[0].v, L.Q.v)})
+  for (int64_t e : {dot_ws_elems(fv, fv), dot_ws_elems(L.Pp[0].v, L.Q.v),
+                    dot_ws_elems(L.R.v, L.Q.v), dot_ws_elems(L.Rr[0].v, L.Q.v)})
     L.dot_elems = e > L.dot_elems ? e : L.dot_elems;
   L.dot_ws = (double *)ar.take(sizeof(double) * L.dot_elems);
   L.sc = (double *)ar.take(sizeof(double) * S_COUNT);
+  if (o->sketch > 0) {
+    const int ell = rin + o->sketch;
+    int64_t e = sketch_ws_elems(L.R.v, ell);
+    e = std::max<int64_t>(e, sketch_ws_elems(L.Rr[0].v, ell));
+    e = std::max<int64_t>(e, sketch_ws_elems(L.Pp[0].v, ell));
+    L.sk_ws = (double *)ar.take(sizeof(double) * e);
+  }
+  // FP64 residual check on the dense grid
+  L.N = 1;
+  for (int k = 0; k < D; ++k) L.N *= n[k];
+  L.dense = (double *)ar.take(sizeof(double) * L.N);
+  std::vector<int32_t> rc(L.R.v.cap, L.R.v.cap + D + 1);
+  L.full_ws = (double *)ar.take(sizeof(double) * full_ws_elems(L.R.v, rc.data()));
   (void)Rk;
   (void)rf;
   return ok && ar.ok();
@@ -121,7 +161,19 @@ qtt_status check_opts(const qtt_solve_opts *o) {
   if (o->maxit_in < 1 || o->maxit_out < 0) return fail(QTT_E_INVAL, "bad iteration limits");
   if (o->compute != QTT_F64 && o->compute != QTT_F32 && o->compute != QTT_BF16)
     return fail(QTT_E_INVAL, "bad compute dtype");
-  if (o->sketch != 0) return fail(QTT_E_UNSUPPORTED, "sketched rounding is not available");
+  if (o->sketch < 0 || o->sketch > 256) return fail(QTT_E_INVAL, "sketch must be in 0..256");
+  return QTT_OK;
+}
+
+qtt_status check_precond(const qtt_tt *K, const qtt_tt *C) {
+  if (!C) return QTT_OK;
+  if (!C->ncol || !C->data || !C->ranks || !C->nrow || C->ncores != K->ncores)
+    return fail(QTT_E_INVAL, "precond must be a QTT matrix with K's cores");
+  for (int k = 0; k < K->ncores; ++k)
+    if (C->nrow[k] != K->nrow[k] || C->ncol[k] != K->ncol[k])
+      return fail(QTT_E_SHAPE, "precond modes differ from K's");
+  if (C->ranks[0] != 1 || C->ranks[C->ncores] != 1)
+    return fail(QTT_E_SHAPE, "precond boundary ranks must be 1");
   return QTT_OK;
 }
 
@@ -148,12 +200,13 @@ extern "C" qtt_status qtt_solve_workspace(const qtt_tt *K, const qtt_tt *f,
   qtt_status st;
   if ((st = check_system(K, f)) != QTT_OK) return st;
   if ((st = check_opts(o)) != QTT_OK) return st;
+  if ((st = check_precond(K, o->precond)) != QTT_OK) return st;
   if (!bytes) return fail(QTT_E_INVAL, "bytes is NULL");
   Arena ar;
   ar.dry = true;
   SolveLayout L;
   carve(ar, K, f, o, L);
-  ar.take(sizeof(int32_t) * 3 * (QTT_MAXD + 1));
+  ar.take(sizeof(int32_t) * 4 * (QTT_MAXD + 1));
   *bytes = ar.used + 4096;
   return QTT_OK;
 }
@@ -164,6 +217,7 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
   qtt_status st;
   if ((st = check_system(K, f)) != QTT_OK) return st;
   if ((st = check_opts(o)) != QTT_OK) return st;
+  if ((st = check_precond(K, o->precond)) != QTT_OK) return st;
   if (!u || !u->data || !u->ranks || u->ncores != K->ncores) return fail(QTT_E_INVAL, "bad u");
   if (x0) {
     if (x0->ncores != K->ncores || x0->ncol || !x0->data) return fail(QTT_E_SHAPE, "bad x0");
@@ -178,7 +232,7 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
   ar.size = ws_bytes;
   SolveLayout L;
   if (!carve(ar, K, f, o, L)) return fail(QTT_E_CAPACITY, "solve workspace too small");
-  int32_t *rk = (int32_t *)ar.take(sizeof(int32_t) * 3 * (QTT_MAXD + 1));
+  int32_t *rk = (int32_t *)ar.take(sizeof(int32_t) * 4 * (QTT_MAXD + 1));
   if (!ar.ok()) return fail(QTT_E_CAPACITY, "solve workspace too small");
   hipStream_t s = (hipStream_t)stream;
   const int D = K->ncores;
@@ -187,13 +241,27 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
   packed_view_of(f, fv, rk + (QTT_MAXD + 1));
   QTT_HIP(upload_ranks(Kv, K->ranks, s));
   QTT_HIP(upload_ranks(fv, f->ranks, s));
+  const bool pre = o->precond != nullptr;
+  TTView Cv;
+  if (pre) {
+    packed_view_of(o->precond, Cv, rk + 3 * (QTT_MAXD + 1));
+    QTT_HIP(upload_ranks(Cv, o->precond->ranks, s));
+  }
   double *sc = L.sc;
   const RoundWs &rw = L.rw;
   QTT_HIP(launch_scalar(SC_SET, sc + S_ONE, nullptr, nullptr, 1.0, s));
-  QTT_HIP(launch_dot(fv, fv, sc + S_FNORM2, L.dot_ws, L.dot_elems, s));
+  QTT_HIP(tt_full(fv, f->ranks, L.dense, L.full_ws, s));
+  QTT_HIP(launch_diff_norm2(L.dense, nullptr, L.N, sc + S_FNORM2, s));
   double fn2 = 0.0;
   QTT_HIP(hipMemcpyAsync(&fn2, sc + S_FNORM2, sizeof(double), hipMemcpyDeviceToHost, s));
   QTT_HIP(hipStreamSynchronize(s));
+  uint64_t call = 0;
+  // QTT_SOLVE_TRACE=1 prints the refinement history to stderr
+  const bool trace = std::getenv("QTT_SOLVE_TRACE") != nullptr;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto secs = [&]() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
   const double fnorm = std::sqrt(fn2 > 0.0 ? fn2 : 0.0);
   qtt_solve_report R;
   std::memset(&R, 0, sizeof(R));
@@ -215,26 +283,55 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
   const qtt_dtype lowp = (qtt_dtype)o->compute;
   bool converged = fnorm == 0.0;
   for (int out = 0; out <= o->maxit_out && fnorm > 0.0; ++out) {
-    // residual r = f - K u (exact product and difference), then rounding
+    // residual r = f - K u (exact product and difference)
     if (have_u) {
       QTT_HIP(launch_matvec(Kv, L.U[cur].v, L.Ku.v, QTT_F64, s));
       QTT_HIP(launch_axpby(1.0, nullptr, fv, -1.0, nullptr, L.Ku.v, L.R.v, s));
     } else {
       QTT_HIP(launch_copy_tt(fv, L.R.v, s));
     }
-    QTT_HIP(round_tt(L.R.v, o->eps_in, o->rmax_in, rw, s));
-    double nr[2];
-    QTT_HIP(hipMemcpyAsync(nr, rw.scal, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
-    QTT_HIP(hipStreamSynchronize(s));
-    const double rel = nr[0] / fnorm;
+    // FP64 check: ||f - K u|| from the exact dense contraction of the
+    // residual train (its ranks are known: f's plus K's times u's)
+    double rel;
+    {
+      int32_t ur[QTT_MAXD + 1];
+      std::vector<int32_t> rr(D + 1);
+      if (have_u) {
+        QTT_HIP(hipMemcpyAsync(ur, L.U[cur].v.rk, sizeof(int32_t) * (D + 1),
+                               hipMemcpyDeviceToHost, s));
+        QTT_HIP(hipStreamSynchronize(s));
+        for (int k = 0; k <= D; ++k) {
+          rr[k] = (k == 0 || k == D) ? 1 : f->ranks[k] + K->ranks[k] * ur[k];
+          if (ur[k] < 1 || ur[k] > L.U[cur].v.cap[k] || rr[k] > L.R.v.cap[k])
+            return fail(QTT_E_CAPACITY, "iterate rank exceeds its buffer");
+        }
+      } else {
+        for (int k = 0; k <= D; ++k) rr[k] = f->ranks[k];
+      }
+      QTT_HIP(tt_full(L.R.v, rr.data(), L.dense, L.full_ws, s));
+      QTT_HIP(launch_diff_norm2(L.dense, nullptr, L.N, sc + S_RES, s));
+      double rn2[2];
+      QTT_HIP(hipMemcpyAsync(rn2, sc + S_RES, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+      QTT_HIP(hipStreamSynchronize(s));
+      rel = std::sqrt(rn2[0]) / fnorm;
+    }
     if (out < 64) R.residual_hist[out] = rel;
     R.residual = rel;
+    if (trace)
+      std::fprintf(stderr, "[qtt_solve] %.3fs outer %d residual %.3e inner total %d\n", secs(), out,
+                   rel, R.inner);
     if (!std::isfinite(rel)) return fail(QTT_E_NOCONV, "residual is not finite");
     if (rel <= o->tol) {
       converged = true;
       break;
     }
     if (out == o->maxit_out) break;
+    // the correction's right-hand side: the residual rounded to (eps_in, rmax_in)
+    if (o->sketch > 0) QTT_HIP(sketch_tt(L.R.v, o->rmax_in + o->sketch, o->seed, call++, L.sk_ws, s));
+    QTT_HIP(round_tt(L.R.v, o->eps_in, o->rmax_in, rw, s));
+    double nr[2];
+    QTT_HIP(hipMemcpyAsync(nr, rw.scal, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+    QTT_HIP(hipStreamSynchronize(s));
     // inner CG on K e = r: x = 0, r_c = r, p = r
     int xi = 0, ri = 0, pi = 0;
     {
@@ -243,38 +340,65 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
       QTT_HIP(hipMemsetAsync(L.X[0].v.data, 0, sizeof(double) * L.X[0].elems, s));
     }
     QTT_HIP(launch_copy_tt(L.R.v, L.Rr[0].v, s));
-    QTT_HIP(launch_copy_tt(L.R.v, L.Pp[0].v, s));
-    // rho = ||r||^2 after the rounding above
-    QTT_HIP(launch_scalar(SC_NORM2, sc + S_RHO, rw.scal, nullptr, 0.0, s));
+    // truncated (P)CG: products exact, sums rounded (see the file comment)
+    auto round_in = [&](const TTView &v) -> hipError_t {
+      hipError_t e = hipSuccess;
+      if (o->sketch > 0) e = sketch_tt(v, o->rmax_in + o->sketch, o->seed, call++, L.sk_ws, s);
+      if (e != hipSuccess) return e;
+      return round_tt(v, o->eps_in, o->rmax_in, rw, s);
+    };
+    if (pre) {
+      // z = C r (exact), rho = <r, z>, p = round(z)
+      QTT_HIP(launch_matvec(Cv, L.R.v, L.Q.v, lowp, s));
+      QTT_HIP(launch_dot(L.R.v, L.Q.v, sc + S_RHO, L.dot_ws, L.dot_elems, s));
+      QTT_HIP(launch_copy_tt(L.Q.v, L.Pp[0].v, s));
+      QTT_HIP(round_in(L.Pp[0].v));
+    } else {
+      QTT_HIP(launch_copy_tt(L.R.v, L.Pp[0].v, s));
+      // rho = ||r||^2 after the rounding above
+      QTT_HIP(launch_scalar(SC_NORM2, sc + S_RHO, rw.scal, nullptr, 0.0, s));
+    }
     const double bn = nr[0] * std::sqrt(std::fmax(1.0 - (nr[1] / (nr[0] * nr[0] + 1e-300)), 0.0));
     int it = 0;
     for (it = 1; it <= o->maxit_in; ++it) {
-      // q = round(K p)
+      // q = K p (exact), alpha = rho / <p, q>
       QTT_HIP(launch_matvec(Kv, L.Pp[pi].v, L.Q.v, lowp, s));
-      QTT_HIP(round_tt(L.Q.v, o->eps_in, o->rmax_in, rw, s));
       QTT_HIP(launch_dot(L.Pp[pi].v, L.Q.v, sc + S_PQ, L.dot_ws, L.dot_elems, s));
       QTT_HIP(launch_scalar(SC_DIV_POS, sc + S_ALPHA, sc + S_RHO, sc + S_PQ, 0.0, s));
-      // x = round(x + alpha p)
+      // x = round(x + alpha p) at the outer accuracy: its truncation error
+      // reaches the true residual multiplied by ||K||
       QTT_HIP(launch_axpby(1.0, nullptr, L.X[xi].v, 1.0, sc + S_ALPHA, L.Pp[pi].v, L.X[1 - xi].v, s));
       xi = 1 - xi;
-      QTT_HIP(round_tt(L.X[xi].v, o->eps_in, o->rmax_in, rw, s));
-      // r = round(r - alpha q); rho_new = ||r||^2
+      QTT_HIP(round_tt(L.X[xi].v, o->eps, o->rmax, rw, s));
+      // r = round(r - alpha q), rounded as one sum; ||r||^2 from the rounding
       QTT_HIP(launch_axpby(1.0, nullptr, L.Rr[ri].v, -1.0, sc + S_ALPHA, L.Q.v, L.Rr[1 - ri].v, s));
       ri = 1 - ri;
-      QTT_HIP(round_tt(L.Rr[ri].v, o->eps_in, o->rmax_in, rw, s));
-      QTT_HIP(launch_scalar(SC_NORM2, sc + S_RHONEW, rw.scal, nullptr, 0.0, s));
+      QTT_HIP(round_in(L.Rr[ri].v));
+      QTT_HIP(launch_scalar(SC_NORM2, sc + S_RES, rw.scal, nullptr, 0.0, s));
       if (it % o->check_every == 0 || it == o->maxit_in) {
-        double rho_new = 0.0;
-        QTT_HIP(hipMemcpyAsync(&rho_new, sc + S_RHONEW, sizeof(double), hipMemcpyDeviceToHost, s));
+        double rr = 0.0;
+        QTT_HIP(hipMemcpyAsync(&rr, sc + S_RES, sizeof(double), hipMemcpyDeviceToHost, s));
         QTT_HIP(hipStreamSynchronize(s));
-        if (!std::isfinite(rho_new)) return fail(QTT_E_NOCONV, "inner residual is not finite");
-        if (std::sqrt(rho_new) <= o->red_in * bn) break;
+        if (!std::isfinite(rr)) return fail(QTT_E_NOCONV, "inner residual is not finite");
+        if (trace && it % 50 == 0)
+          std::fprintf(stderr, "[qtt_solve] %.3fs   inner %d ||r||/||b|| %.3e\n", secs(), it,
+                       std::sqrt(rr) / bn);
+        if (std::sqrt(rr) <= o->red_in * bn) break;
       }
-      // p = round(r + beta p)
+      const TTView *zv = &L.Rr[ri].v;
+      if (pre) {
+        // z = C r (exact), rho_new = <r, z>
+        QTT_HIP(launch_matvec(Cv, L.Rr[ri].v, L.Q.v, lowp, s));
+        QTT_HIP(launch_dot(L.Rr[ri].v, L.Q.v, sc + S_RHONEW, L.dot_ws, L.dot_elems, s));
+        zv = &L.Q.v;
+      } else {
+        QTT_HIP(launch_scalar(SC_COPY, sc + S_RHONEW, sc + S_RES, nullptr, 0.0, s));
+      }
+      // p = round(z + beta p), rounded as one sum
       QTT_HIP(launch_scalar(SC_DIV, sc + S_BETA, sc + S_RHONEW, sc + S_RHO, 0.0, s));
-      QTT_HIP(launch_axpby(1.0, nullptr, L.Rr[ri].v, 1.0, sc + S_BETA, L.Pp[pi].v, L.Pp[1 - pi].v, s));
+      QTT_HIP(launch_axpby(1.0, nullptr, *zv, 1.0, sc + S_BETA, L.Pp[pi].v, L.Pp[1 - pi].v, s));
       pi = 1 - pi;
-      QTT_HIP(round_tt(L.Pp[pi].v, o->eps_in, o->rmax_in, rw, s));
+      QTT_HIP(round_in(L.Pp[pi].v));
       QTT_HIP(launch_scalar(SC_COPY, sc + S_RHO, sc + S_RHONEW, nullptr, 0.0, s));
     }
     R.inner += it > o->maxit_in ? o->maxit_in : it;

@@ -71,6 +71,8 @@ def test_matvec_low_precision(P, compute, tol):
     ([2] * 10, 20, 0.0, 6),
     ([4] * 5, 12, 1e-8, 0),
     ([2] * 8, 70, 1e-12, 0),                 # unfoldings larger than a tile
+    ([2] * 16, 128, 1e-10, 0),               # Jacobi with logged rotations replayed
+    ([2] * 16, 128, 1e-3, 40),
 ])
 def test_round_matches_oracle(P, modes, r, eps, rmax):
     y = _vec(7, modes, r)
@@ -150,3 +152,26 @@ def test_matvec_level10_shapes_sampled(P):
     for k in (0, 1, 7, 10, 15, 20):
         ref = T.matvec([Kq[k]], [x[k]])[0]
         assert np.abs(got[k] - ref).max() <= 2e-15 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("ell,eps", [(12, 1e-6), (30, 1e-10)])
+def test_sketch_rounding_against_exact(P, ell, eps):
+    """Randomised rounding (Gaussian sketch of rank ell, then the exact
+    rounding) of a matvec product: its error against the exact tensor is close
+    to the oracle's best error at the same final ranks."""
+    from oracle import assembly as A
+    prob = W.cantilever_traction(5)
+    Kq, fq = A.assemble_qtt(prob)
+    x = T.tt_round(_vec(3, [2] * 11, 6), 0.0)
+    y = T.matvec(Kq, x)
+    yd = T.full_vector(y)
+    ref, info = T.tt_round(y, eps, return_info=True)
+    t = P.matvec(P.tt_from_cores(Kq), P.tt_from_cores(x))
+    nrm, err = P.round_sketch(t, ell, 11, eps, 0)
+    gd = T.full_vector(P.tt_to_cores(t))
+    assert max(t.ranks) <= ell
+    # the sketch captures the dominant subspace: the error is at most a
+    # small multiple of the rank-ell optimum plus the requested accuracy
+    opt, _ = T.tt_round(y, 0.0, ell, return_info=True)
+    best = np.linalg.norm(T.full_vector(opt) - yd)
+    assert np.linalg.norm(gd - yd) <= 10 * best + 2 * eps * np.linalg.norm(yd)
