@@ -168,6 +168,8 @@ qtt_status qtt_round_workspace(const qtt_tt *x, int32_t rmax, size_t *bytes);
 qtt_status qtt_round_sketch(qtt_tt *x, int32_t ell, uint64_t seed, double eps, int32_t rmax,
                             double *norm, double *err, void *ws, size_t ws_bytes,
                             void *stream);
+/* Workspace bytes of qtt_round_sketch for x's current ranks and `ell`.    */
+qtt_status qtt_round_sketch_workspace(const qtt_tt *x, int32_t ell, size_t *bytes);
 
 /* qtt_dot — <x, y> of two TT vectors of equal modes (left-to-right
  * environment sweep).  Synchronises `stream`.                              */
@@ -182,44 +184,71 @@ qtt_status qtt_axpby(double a, const qtt_tt *x, double b, const qtt_tt *y,
                      qtt_tt *z, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------ solve   */
+typedef enum {
+  QTT_SOLVE_CG_IR = 0,     /* truncated CG with FP64 iterative refinement      */
+  QTT_SOLVE_CHEBYSHEV = 1  /* preconditioned Chebyshev iteration, true residual
+                              every step (needs `precond`)                      */
+} qtt_solve_method;
+
 typedef struct {
-  double tol;        /* stop when ||f - K u|| <= tol ||f|| (FP64)            */
+  double tol;        /* CG_IR: stop when ||f - K u|| <= tol ||f|| (FP64).
+                        CHEBYSHEV: stop when sqrt(<r, C r>) <= tol sqrt(<f, C f>)
+                        with r = f - K u: the preconditioned residual, equal to
+                        the relative energy-norm error within sqrt(lmax/lmin) */
   double eps;        /* rounding accuracy of the iterate u                    */
   int32_t rmax;      /* rank cap of u                                         */
-  double eps_in;     /* rounding accuracy inside the correction solve         */
-  int32_t rmax_in;   /* rank cap inside the correction solve                  */
-  double red_in;     /* relative residual reduction of each correction solve  */
-  int32_t maxit_in;  /* CG iterations per correction solve                   */
-  int32_t maxit_out; /* refinement steps                                      */
-  int32_t check_every; /* CG iterations between host convergence checks      */
+  double eps_in;     /* rounding accuracy of the residual, the preconditioned
+                        residual and the search direction (relative to each
+                        vector's own norm)                                    */
+  int32_t rmax_in;   /* rank cap of those vectors (<= rmax for CHEBYSHEV)    */
+  double red_in;     /* CG_IR: residual reduction of each correction solve   */
+  int32_t maxit_in;  /* CG_IR: CG iterations per correction solve;
+                        CHEBYSHEV: iterations in total                        */
+  int32_t maxit_out; /* CG_IR: refinement steps                              */
+  int32_t check_every; /* iterations between host convergence checks        */
   qtt_dtype compute; /* contractions: QTT_F64, QTT_F32 or QTT_BF16 (QR, SVD,
                         dot products and the outer residual stay FP64)       */
-  int32_t sketch;    /* 0: exact rounding of every product K p; > 0: round
+  int32_t sketch;    /* 0: exact rounding of every product; > 0: round
                         products by a randomised sketch of this oversampling
                         before the exact rounding                            */
   uint64_t seed;     /* seed of the sketch generator (Philox4x32-10)         */
   const qtt_tt *precond; /* NULL, or a QTT matrix C ~ K^-1 (symmetric positive
-                        definite, e.g. from qtt_assemble_bpx): the correction
-                        solve is then preconditioned CG with z = round(C r) */
+                        definite, e.g. from qtt_assemble_bpx)                */
+  int32_t method;    /* qtt_solve_method                                     */
+  double lmin;       /* CHEBYSHEV: lower bound of the spectrum of C K; <= 0
+                        takes 0.09, the bound measured for qtt_assemble_bpx's
+                        operator on the cantilever family (levels 2..6)      */
+  double lmax;       /* CHEBYSHEV: upper bound of the spectrum of C K; <= 0
+                        estimates it by 12 power steps on C K started from f,
+                        times 1.12 (reported back in the report)            */
 } qtt_solve_opts;
 
 typedef struct {
   int32_t status;         /* QTT_OK or QTT_E_NOCONV                           */
-  int32_t outer;          /* refinement steps taken                           */
-  int32_t inner;          /* CG iterations in total                           */
-  double residual;        /* final ||f - K u|| / ||f|| in FP64                */
-  double residual_hist[64]; /* residual before each refinement step         */
+  int32_t outer;          /* CG_IR: refinement steps taken                    */
+  int32_t inner;          /* CG iterations (CG_IR) or Chebyshev iterations    */
+  double residual;        /* final ||f - K u|| / ||f|| in FP64 (dense check)  */
+  double residual_hist[64]; /* CG_IR: residual before each refinement step;
+                             CHEBYSHEV: stop criterion at each check        */
   int32_t max_rank;       /* largest bond rank of u                           */
+  double criterion;       /* value of the stop criterion at exit              */
+  double lmax;            /* CHEBYSHEV: the upper spectral bound used         */
 } qtt_solve_report;
 
-/* qtt_solve — solve K u = f (K symmetric positive definite) by conjugate
- * gradients on the QTT format with FP64 iterative refinement: the outer
- * loop forms the residual f - K u exactly (product, difference) and rounds
- * it, the inner loop runs CG on K e = r with every iterate rounded to
- * (eps_in, rmax_in), and u <- round(u + e, eps, rmax).  x0 (NULL: zero) is
- * the starting guess.  u must have capacity for rank rmax.  Writes u->ranks
- * and the report.  Synchronises `stream`.  Returns QTT_E_NOCONV (with the
- * last iterate in u) when maxit_out is reached.                            */
+/* qtt_solve — solve K u = f (K symmetric positive definite) on the QTT
+ * format with every iterate rounded.
+ * CG_IR: the outer loop forms the residual f - K u exactly (product,
+ * difference), checks its FP64 norm and rounds it; the inner loop runs
+ * truncated (P)CG on K e = r with its vectors rounded to (eps_in, rmax_in);
+ * u <- round(u + e, eps, rmax).
+ * CHEBYSHEV: u_{k+1} = u_k + d_k with d_k = c1 d_{k-1} + c2 round(C r_k),
+ * r_k = round(f - K u_k) recomputed from u_k at every step (so rounding
+ * errors do not accumulate in a recurrence), c1, c2 from the Chebyshev
+ * polynomials on [lmin, lmax] (Golub-Varga two-term form).
+ * x0 (NULL: zero) is the starting guess.  u must have capacity for rank
+ * rmax.  Writes u->ranks and the report.  Synchronises `stream`.  Returns
+ * QTT_E_NOCONV (with the last iterate in u) when the iteration limit is
+ * reached.                                                                 */
 qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
                      const qtt_solve_opts *opts, qtt_tt *u,
                      qtt_solve_report *report, void *ws, size_t ws_bytes,

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libqtt.so")
 
 QTT_F64, QTT_F32, QTT_BF16 = 0, 1, 2
 _DTYPES = {"f64": QTT_F64, "f32": QTT_F32, "bf16": QTT_BF16}
+_METHODS = {"cg": 0, "chebyshev": 1}
 MAX_CORES = 40
 
 
@@ -50,13 +51,14 @@ class _SolveOpts(C.Structure):
                 ("eps_in", C.c_double), ("rmax_in", C.c_int32), ("red_in", C.c_double),
                 ("maxit_in", C.c_int32), ("maxit_out", C.c_int32),
                 ("check_every", C.c_int32), ("compute", C.c_int32),
-                ("sketch", C.c_int32), ("seed", C.c_uint64), ("precond", C.POINTER(_TT))]
+                ("sketch", C.c_int32), ("seed", C.c_uint64), ("precond", C.POINTER(_TT)),
+                ("method", C.c_int32), ("lmin", C.c_double), ("lmax", C.c_double)]
 
 
 class _SolveReport(C.Structure):
     _fields_ = [("status", C.c_int32), ("outer", C.c_int32), ("inner", C.c_int32),
                 ("residual", C.c_double), ("residual_hist", C.c_double * 64),
-                ("max_rank", C.c_int32)]
+                ("max_rank", C.c_int32), ("criterion", C.c_double), ("lmax", C.c_double)]
 
 
 _lib = None
@@ -81,6 +83,7 @@ def load_library(path: str = LIB_PATH):
     L.qtt_round_workspace.argtypes = [P(_TT), C.c_int32, P(sz)]
     L.qtt_round_sketch.argtypes = [P(_TT), C.c_int32, C.c_uint64, C.c_double, C.c_int32,
                                    P(C.c_double), P(C.c_double), vp, sz, vp]
+    L.qtt_round_sketch_workspace.argtypes = [P(_TT), C.c_int32, P(sz)]
     L.qtt_dot.argtypes = [P(_TT), P(_TT), P(C.c_double), vp, sz, vp]
     L.qtt_axpby.argtypes = [C.c_double, P(_TT), C.c_double, P(_TT), P(_TT), vp, sz, vp]
     L.qtt_assemble_stiffness.argtypes = [P(_Problem), C.c_double, P(_TT), P(_TT), vp, sz, vp]
@@ -90,6 +93,7 @@ def load_library(path: str = LIB_PATH):
                             vp, sz, vp]
     L.qtt_solve_workspace.argtypes = [P(_TT), P(_TT), P(_SolveOpts), P(sz)]
     for name in ("qtt_matvec", "qtt_round", "qtt_round_workspace", "qtt_round_sketch",
+                 "qtt_round_sketch_workspace",
                  "qtt_dot", "qtt_axpby",
                  "qtt_assemble_stiffness", "qtt_assemble_workspace", "qtt_assemble_bpx", "qtt_solve",
                  "qtt_solve_workspace"):
@@ -235,10 +239,8 @@ def round_sketch(x: TT, ell: int, seed: int, eps: float, rmax: int = 0):
     """Randomised rounding in place (Gaussian sketch of rank ell, then the
     exact rounding); returns (norm, discarded bound) of the exact step."""
     need = C.c_size_t()
-    _check(lib().qtt_round_workspace(C.byref(x.c), int(rmax), C.byref(need)))
-    D = x.D
-    extra = 8 * (4 * max(x.ranks) * max(x.nrow) * ell * D + 8 * ell * ell * max(x.nrow) + 4 * max(x.ranks) * max(x.nrow) * ell * 4) + (1 << 20)
-    ws = _workspace(need.value + extra)
+    _check(lib().qtt_round_sketch_workspace(C.byref(x.c), int(ell), C.byref(need)))
+    ws = _workspace(need.value)
     nrm, err = C.c_double(), C.c_double()
     _check(lib().qtt_round_sketch(C.byref(x.c), int(ell), int(seed), float(eps), int(rmax),
                                   C.byref(nrm), C.byref(err), C.c_void_p(_aligned_ptr(ws)),
@@ -346,12 +348,16 @@ class SolveOpts:
     sketch: int = 0
     seed: int = 0
     precond: Optional["TT"] = None
+    method: str = "cg"          # "cg" (CG with refinement) or "chebyshev"
+    lmin: float = 0.0
+    lmax: float = 0.0
 
     def c(self) -> _SolveOpts:
         pc = C.pointer(self.precond.c) if self.precond is not None else None
         return _SolveOpts(self.tol, self.eps, self.rmax, self.eps_in, self.rmax_in,
                           self.red_in, self.maxit_in, self.maxit_out, self.check_every,
-                          _DTYPES[self.compute], self.sketch, self.seed, pc)
+                          _DTYPES[self.compute], self.sketch, self.seed, pc,
+                          _METHODS[self.method], self.lmin, self.lmax)
 
 
 def solve_workspace_bytes(K: TT, f: TT, opts: SolveOpts) -> int:
@@ -375,8 +381,9 @@ def solve(K: TT, f: TT, opts: SolveOpts, x0: Optional[TT] = None, ws=None):
                          C.c_void_p(_aligned_ptr(ws)), ws.numel() - 256, _stream_ptr())
     if st not in (0, -4):
         _check(st)
+    nh = rep.outer + 1 if opts.method == "cg" else rep.inner // max(opts.check_every, 1) + 1
     report = dict(status=rep.status, outer=rep.outer, inner=rep.inner,
                   residual=rep.residual,
-                  residual_hist=[rep.residual_hist[i] for i in range(min(rep.outer + 1, 64))],
-                  max_rank=rep.max_rank)
+                  residual_hist=[rep.residual_hist[i] for i in range(min(nh, 64))],
+                  max_rank=rep.max_rank, criterion=rep.criterion, lmax=rep.lmax)
     return u, report

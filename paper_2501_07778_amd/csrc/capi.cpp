@@ -227,6 +227,24 @@ qtt_status qtt_round(qtt_tt *x, double eps, int32_t rmax, double *norm,
   return QTT_OK;
 }
 
+qtt_status qtt_round_sketch_workspace(const qtt_tt *x, int32_t ell, size_t *bytes) {
+  qtt_status st;
+  if ((st = check_tt(x, "x", true)) != QTT_OK) return st;
+  if (x->ncol) return fail(QTT_E_INVAL, "x must be a vector");
+  if (ell < 1 || ell > 512) return fail(QTT_E_INVAL, "ell must be in 1..512");
+  if (!bytes) return fail(QTT_E_INVAL, "bytes is NULL");
+  Arena ar;
+  ar.dry = true;
+  TTDesc t;
+  std::vector<int> caps(x->ranks, x->ranks + x->ncores + 1);
+  arena_tt(ar, t, x->ncores, x->nrow, x->ncol, caps);
+  RoundWs w;
+  round_ws_take(ar, t.v, w);
+  ar.take(sizeof(double) * sketch_ws_elems(t.v, ell));
+  *bytes = ar.used + 256;
+  return QTT_OK;
+}
+
 qtt_status qtt_round_sketch(qtt_tt *x, int32_t ell, uint64_t seed, double eps, int32_t rmax,
                             double *norm, double *err, void *ws, size_t ws_bytes,
                             void *stream) {
@@ -251,7 +269,7 @@ qtt_status qtt_round_sketch(qtt_tt *x, int32_t ell, uint64_t seed, double eps, i
   QTT_HIP(upload_ranks(t.v, x->ranks, s));
   QTT_HIP(launch_unpack(x->data, t.v, s));
   QTT_HIP(sketch_tt(t.v, ell, seed, 0, sk, s));
-  QTT_HIP(round_tt(t.v, eps, rmax, w, s));
+  QTT_HIP(round_tt(t.v, eps, rmax, w, s, true, ell));
   QTT_HIP(launch_pack(t.v, x->data, s));
   int32_t rk_host[QTT_MAXD + 1];
   double scal[2];

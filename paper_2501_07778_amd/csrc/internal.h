@@ -99,10 +99,16 @@ hipError_t launch_copy_tt(const TTView &src, const TTView &dst,
 hipError_t launch_axpby(double a, const double *a_dev, const TTView &x,
                         double b, const double *b_dev, const TTView &y,
                         const TTView &z, hipStream_t s);
+// v <- c v (the first core is scaled)
+hipError_t launch_scale(const TTView &v, double c, hipStream_t s);
 // <x, y> into *out (device), workspace of `ws_elems` doubles
 hipError_t launch_dot(const TTView &x, const TTView &y, double *out,
                       double *ws, int64_t ws_elems, hipStream_t s);
 int64_t dot_ws_elems(const TTView &x, const TTView &y);
+// <x, A y> (A a TT matrix) without forming A y; ws of dot3_ws_elems doubles
+hipError_t launch_dot3(const TTView &x, const TTView &A, const TTView &y, double *out,
+                       double *ws, int64_t ws_elems, hipStream_t s);
+int64_t dot3_ws_elems(const TTView &x, const TTView &A, const TTView &y);
 // tiny scalar programs on device scalars
 hipError_t launch_scalar(int op, double *s0, const double *s1,
                          const double *s2, double c, hipStream_t s);
@@ -128,8 +134,11 @@ bool round_ws_take(Arena &ar, const TTView &x, RoundWs &w);
 // rounds x in place: ranks stay on the device; norm -> w.scal[0],
 // sum of discarded sigma^2 -> w.scal[1].  eps_dev (may be NULL) replaces
 // eps by *eps_dev (device scalar).
+// left_orth: cores 0..D-2 are already left-orthogonal (e.g. the output of
+// sketch_tt), so the QR sweep is skipped.  rank_bound > 0: the device ranks
+// are known to be <= rank_bound (it selects faster kernel variants).
 hipError_t round_tt(const TTView &x, double eps, int rmax, const RoundWs &w,
-                    hipStream_t s);
+                    hipStream_t s, bool left_orth = false, int rank_bound = 0);
 
 // randomised rounding of y to ranks <= ell (Gaussian sketch, seed/call
 // select the random numbers); ws holds sketch_ws_elems(y, ell) doubles

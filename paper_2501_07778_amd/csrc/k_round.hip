@@ -77,6 +77,17 @@ __global__ void k_round_init(TTView x, int *iwork, double *scal) {
   }
 }
 
+// carry <- last core (input already left-orthogonal: no QR sweep)
+__global__ void k_last_to_carry(TTView x, double *carry) {
+  const int D = x.D;
+  if (x.rk[D - 1] > x.cap[D - 1]) return;
+  const int64_t ne = (int64_t)x.rk[D - 1] * x.n[D - 1] * x.m[D - 1];
+  const double *c = x.data + x.off[D - 1];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x)
+    carry[e] = c[e];
+}
+
 // Householder QR of a column-major rows x cols matrix W (ld = rows) in
 // place: R above the diagonal, reflectors below, tau[j].  LAPACK-style
 // reflectors H = I - tau v v^T with v(0) = 1.
@@ -614,7 +625,12 @@ bool round_ws_take(Arena &ar, const TTView &x, RoundWs &w) {
 }
 
 hipError_t round_tt(const TTView &x, double eps, int rmax, const RoundWs &w,
-                    hipStream_t s) {
+                    hipStream_t s, bool left_orth, int rank_bound) {
+  // the kernel variants are chosen from bounds on the ranks: the slot caps,
+  // tightened by rank_bound when the caller knows one
+  auto cap_of = [&](int k) {
+    return (rank_bound > 0 && rank_bound < x.cap[k]) ? rank_bound : x.cap[k];
+  };
   const int D = x.D;
   if (D == 1) {
     hipLaunchKernelGGL(k_round_single, dim3(1), dim3(WG), 0, s, x, w.scal);
@@ -625,10 +641,16 @@ hipError_t round_tt(const TTView &x, double eps, int rmax, const RoundWs &w,
   const int cap = max_cap(x);
   const int nmx = max_nm(x);
   hipLaunchKernelGGL(k_round_init, dim3(1), dim3(64), 0, s, x, w.iwork, w.scal);
-  for (int k = 0; k < D - 1; ++k) {
+  if (left_orth) {
+    const int64_t ne = (int64_t)x.cap[D - 1] * x.n[D - 1] * x.m[D - 1];
+    const int blocks = (int)std::min<int64_t>((ne + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_last_to_carry, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, x,
+                       w.carry);
+  }
+  for (int k = 0; k < D - 1 && !left_orth; ++k) {
     const double *src = (k == 0) ? x.data + x.off[0] : w.carry;
-    const int64_t rc = (int64_t)x.cap[k] * x.n[k] * x.m[k];
-    const int64_t cc = x.cap[k + 1];
+    const int64_t rc = (int64_t)cap_of(k) * x.n[k] * x.m[k];
+    const int64_t cc = cap_of(k + 1);
     if (rc * cc <= LDS_DBL && (rc < cc ? rc : cc) <= LDS_TAU)
       hipLaunchKernelGGL(k_qr_step<true>, dim3(1), dim3(WG), 0, s, x, k, src, w.work,
                          w.rbuf, tau, w.iwork);
@@ -644,8 +666,8 @@ hipError_t round_tt(const TTView &x, double eps, int rmax, const RoundWs &w,
                      w.scal);
   for (int k = D - 1; k >= 1; --k) {
     // fr[k+1] <= min(cap, rmax): the truncation already happened to its right
-    const int64_t frc = (rmax > 0 && rmax < x.cap[k + 1]) ? rmax : x.cap[k + 1];
-    const int64_t r0c = x.cap[k];
+    const int64_t frc = (rmax > 0 && rmax < cap_of(k + 1)) ? rmax : cap_of(k + 1);
+    const int64_t r0c = cap_of(k);
     const int64_t ncc = (int64_t)x.n[k] * x.m[k] * frc;
     const int64_t nbc = r0c < ncc ? r0c : ncc;
     const int64_t mbc = r0c > ncc ? r0c : ncc;

@@ -9,6 +9,8 @@
 // operand values kept in registers.
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace qtt {
@@ -246,6 +248,89 @@ __global__ void __launch_bounds__(DOT_THREADS)
   if (threadIdx.x == 0) *out = phi[0];
 }
 
+// <x, A y> for TT vectors x, y and a TT matrix A: left environment
+// Phi_{k+1}[b, beta, b'] = sum x_k[a,i,b] A_k[alpha,i,j,beta] y_k[a',j,b']
+// Phi_k[a, alpha, a'], three contractions per core, one block.  The cost is
+// O(r^3 R n + r^2 R^2 n^2) per core instead of the O(r (R r)^2 n) of <x, z>
+// with z = A y formed first.  ws: Phi (phi_cap) then W1, W2 (w_cap each).
+__global__ void __launch_bounds__(DOT_THREADS)
+    k_dot3(TTView x, TTView A, TTView y, double *out, double *ws, int64_t phi_cap,
+           int64_t w_cap) {
+  double *phi = ws;
+  double *W1 = ws + phi_cap;
+  double *W2 = W1 + w_cap;
+  const int D = x.D;
+  for (int k = 0; k <= D; ++k)
+    if (x.rk[k] > x.cap[k] || y.rk[k] > y.cap[k] || A.rk[k] > A.cap[k]) {
+      if (threadIdx.x == 0) *out = NAN;
+      return;
+    }
+  if (threadIdx.x == 0) phi[0] = 1.0;
+  __syncthreads();
+  for (int k = 0; k < D; ++k) {
+    const int rx0 = x.rk[k], rx1 = x.rk[k + 1];
+    const int ry0 = y.rk[k], ry1 = y.rk[k + 1];
+    const int ra0 = A.rk[k], ra1 = A.rk[k + 1];
+    const int n = x.n[k];
+    const double *xk = x.data + x.off[k];
+    const double *yk = y.data + y.off[k];
+    const double *ak = A.data + A.off[k];
+    // W1[a, al, j, b'] = sum_a' Phi[a, al, a'] y[a', j, b']
+    const int64_t n1 = (int64_t)rx0 * ra0 * n * ry1;
+    for (int64_t e = threadIdx.x; e < n1; e += blockDim.x) {
+      const int aal = (int)(e % ((int64_t)rx0 * ra0));
+      const int jb = (int)(e / ((int64_t)rx0 * ra0));
+      const double *yc = yk + (int64_t)ry0 * jb;
+      double acc = 0.0;
+      for (int a2 = 0; a2 < ry0; ++a2) acc = fma(phi[aal + (int64_t)rx0 * ra0 * a2], yc[a2], acc);
+      W1[e] = acc;
+    }
+    __syncthreads();
+    // W2[a, i, be, b'] = sum_{al, j} W1[a, al, j, b'] A[al, i, j, be]
+    const int64_t n2 = (int64_t)rx0 * n * ra1 * ry1;
+    for (int64_t e = threadIdx.x; e < n2; e += blockDim.x) {
+      const int a = (int)(e % rx0);
+      int64_t t = e / rx0;
+      const int i = (int)(t % n);
+      t /= n;
+      const int be = (int)(t % ra1);
+      const int b2 = (int)(t / ra1);
+      double acc = 0.0;
+      for (int j = 0; j < n; ++j) {
+        const double *w = W1 + a + (int64_t)rx0 * ra0 * (j + (int64_t)n * b2);
+        const double *av = ak + (int64_t)ra0 * (i + (int64_t)n * (j + (int64_t)n * be));
+        for (int al = 0; al < ra0; ++al) acc = fma(w[(int64_t)rx0 * al], av[al], acc);
+      }
+      W2[e] = acc;
+    }
+    __syncthreads();
+    // Phi'[b, be, b'] = sum_{a, i} x[a, i, b] W2[a, i, be, b']
+    const int L = rx0 * n;
+    const int64_t n3 = (int64_t)rx1 * ra1 * ry1;
+    for (int64_t e = threadIdx.x; e < n3; e += blockDim.x) {
+      const int b = (int)(e % rx1);
+      const int64_t col = e / rx1;  // be + ra1 b'
+      const double *xc = xk + (int64_t)L * b;
+      const double *wc = W2 + (int64_t)L * col;
+      double acc = 0.0;
+      for (int l = 0; l < L; ++l) acc = fma(xc[l], wc[l], acc);
+      phi[e] = acc;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = phi[0];
+}
+
+// core 0 of a TT vector times c (ranks from the device)
+__global__ void k_scale_first(TTView v, double c) {
+  if (v.rk[1] > v.cap[1]) return;
+  const int64_t ne = (int64_t)v.n[0] * v.m[0] * v.rk[1];
+  double *c0 = v.data + v.off[0];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x)
+    c0[e] *= c;
+}
+
 __global__ void k_scalar(int op, double *s0, const double *s1,
                          const double *s2, double c) {
   switch (op) {
@@ -278,6 +363,13 @@ int64_t max_core_cap(const TTView &v) {
 }
 
 }  // namespace
+
+hipError_t launch_scale(const TTView &v, double c, hipStream_t s) {
+  const int64_t ne = (int64_t)v.n[0] * v.m[0] * v.cap[1];
+  const int blocks = (int)std::min<int64_t>((ne + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_scale_first, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, v, c);
+  return hipGetLastError();
+}
 
 hipError_t launch_matvec(const TTView &A, const TTView &x, const TTView &y,
                          qtt_dtype compute, hipStream_t s) {
@@ -347,6 +439,37 @@ hipError_t launch_dot(const TTView &x, const TTView &y, double *out,
   }
   hipLaunchKernelGGL(k_dot, dim3(1), dim3(DOT_THREADS), 0, s, x, y, out, ws,
                      phi_cap);
+  return hipGetLastError();
+}
+
+void dot3_caps(const TTView &x, const TTView &A, const TTView &y, int64_t &phi, int64_t &w) {
+  phi = 1;
+  w = 1;
+  for (int k = 0; k <= x.D; ++k) {
+    int64_t c = (int64_t)x.cap[k] * A.cap[k] * y.cap[k];
+    phi = c > phi ? c : phi;
+  }
+  for (int k = 0; k < x.D; ++k) {
+    const int64_t n = x.n[k];
+    int64_t c1 = (int64_t)x.cap[k] * A.cap[k] * n * y.cap[k + 1];
+    int64_t c2 = (int64_t)x.cap[k] * n * A.cap[k + 1] * y.cap[k + 1];
+    w = c1 > w ? c1 : w;
+    w = c2 > w ? c2 : w;
+  }
+}
+
+int64_t dot3_ws_elems(const TTView &x, const TTView &A, const TTView &y) {
+  int64_t phi, w;
+  dot3_caps(x, A, y, phi, w);
+  return phi + 2 * w;
+}
+
+hipError_t launch_dot3(const TTView &x, const TTView &A, const TTView &y, double *out,
+                       double *ws, int64_t ws_elems, hipStream_t s) {
+  int64_t phi, w;
+  dot3_caps(x, A, y, phi, w);
+  if (phi + 2 * w > ws_elems) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dot3, dim3(1), dim3(DOT_THREADS), 0, s, x, A, y, out, ws, phi, w);
   return hipGetLastError();
 }
 

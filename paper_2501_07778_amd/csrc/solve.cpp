@@ -1,10 +1,19 @@
-// solve.cpp — qtt_solve: conjugate gradients on the QTT format with FP64
-// iterative refinement, driven by the QTT matrix-vector product and TT
-// rounding.
+// solve.cpp — qtt_solve: iterative solvers on the QTT format driven by the
+// QTT matrix-vector product and TT rounding.
 //
 // The paper solves K u = f with AMEn (Sec. 3.5, Sec. 4), which it cites but
-// does not describe; this solve is built from the two operations of the
-// format instead:
+// does not describe; these solves are built from the two operations of the
+// format instead.
+//
+// CHEBYSHEV (for fine grids, with the BPX preconditioner C): Chebyshev
+// semi-iteration on C K u = C f with the residual r = f - K u recomputed
+// from the iterate at every step (exact product, then rounding relative to
+// ||r||), z = round(C r), d = c1 d + c2 z, u = round(u + d).  No quantity is
+// updated by a recurrence that rounding could corrupt, so truncation only
+// perturbs each step; the coefficients depend only on the spectral bounds
+// and are computed on the host.  Stop: sqrt(<r, C r>) <= tol sqrt(<f, C f>).
+//
+// CG_IR (small grids):
 //   outer (FP64):  r = round(f - K u); stop when ||f - K u|| <= tol ||f||
 //                  (the norm of the unrounded difference comes out of the
 //                  rounding's QR sweep); e = CG(K, r); u = round(u + e)
@@ -37,6 +46,7 @@ namespace {
 
 struct SolveLayout {
   TTDesc U[2], Ku, R, X[2], Rr[2], Pp[2], Q;
+  TTView Rin, Pin;  // R and Pp[0] with the caps of a rounded inner vector
   RoundWs rw;
   double *dot_ws = nullptr;
   int64_t dot_elems = 0;
@@ -48,7 +58,8 @@ struct SolveLayout {
 };
 
 enum {
-  S_FNORM2 = 0, S_RHO, S_PQ, S_ALPHA, S_BETA, S_RHONEW, S_ONE, S_RES, S_COUNT = 16
+  S_FNORM2 = 0, S_RHO, S_PQ, S_ALPHA, S_BETA, S_RHONEW, S_ONE, S_RES, S_PK, S_CR,
+  S_COUNT = 16
 };
 
 std::vector<int> caps_for(const qtt_tt *K, int r) {
@@ -111,8 +122,23 @@ bool carve(Arena &ar, const qtt_tt *K, const qtt_tt *f, const qtt_solve_opts *o,
   for (int k = 0; k <= D; ++k) fv.cap[k] = cf[k];
   L.dot_elems = dot_ws_elems(L.R.v, L.R.v);
   for (int64_t e : {dot_ws_elems(fv, fv), dot_ws_elems(L.Pp[0].v, L.Q.v),
-                    dot_ws_elems(L.R.v, L.Q.v), dot_ws_elems(L.Rr[0].v, L.Q.v)})
+                    dot_ws_elems(L.R.v, L.Q.v), dot_ws_elems(L.Rr[0].v, L.Q.v),
+                    dot_ws_elems(L.Pp[0].v, L.Ku.v)})
     L.dot_elems = e > L.dot_elems ? e : L.dot_elems;
+  // <r, C r> and <v, K v> of the Chebyshev solve, without the products:
+  // r and v are rounded to rmax_in first
+  {
+    L.Rin = L.R.v;
+    L.Pin = L.Pp[0].v;
+    TTView Kc = L.R.v, Cc = L.R.v;
+    for (int k = 0; k <= D; ++k) {
+      L.Rin.cap[k] = L.Pin.cap[k] = ci[k];
+      Kc.cap[k] = K->ranks[k];
+      Cc.cap[k] = o->precond ? o->precond->ranks[k] : 1;
+    }
+    for (int64_t e : {dot3_ws_elems(L.Rin, Cc, L.Rin), dot3_ws_elems(L.Pin, Kc, L.Pin)})
+      L.dot_elems = e > L.dot_elems ? e : L.dot_elems;
+  }
   L.dot_ws = (double *)ar.take(sizeof(double) * L.dot_elems);
   L.sc = (double *)ar.take(sizeof(double) * S_COUNT);
   if (o->sketch > 0) {
@@ -162,6 +188,16 @@ qtt_status check_opts(const qtt_solve_opts *o) {
   if (o->compute != QTT_F64 && o->compute != QTT_F32 && o->compute != QTT_BF16)
     return fail(QTT_E_INVAL, "bad compute dtype");
   if (o->sketch < 0 || o->sketch > 256) return fail(QTT_E_INVAL, "sketch must be in 0..256");
+  if (o->method != QTT_SOLVE_CG_IR && o->method != QTT_SOLVE_CHEBYSHEV)
+    return fail(QTT_E_INVAL, "unknown solve method");
+  if (o->method == QTT_SOLVE_CHEBYSHEV) {
+    if (!o->precond) return fail(QTT_E_INVAL, "the Chebyshev solve needs a preconditioner");
+    if (o->rmax_in > o->rmax) return fail(QTT_E_INVAL, "Chebyshev solve: rmax_in must be <= rmax");
+    if (o->check_every < 1) return fail(QTT_E_INVAL, "check_every must be >= 1");
+    const double lmin = o->lmin > 0.0 ? o->lmin : 0.09;
+    if (o->lmax > 0.0 && !(o->lmax > lmin))
+      return fail(QTT_E_INVAL, "Chebyshev solve: lmax must exceed lmin");
+  }
   return QTT_OK;
 }
 
@@ -282,7 +318,139 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
   }
   const qtt_dtype lowp = (qtt_dtype)o->compute;
   bool converged = fnorm == 0.0;
-  for (int out = 0; out <= o->maxit_out && fnorm > 0.0; ++out) {
+  // sketch (if enabled) then exact rounding to (eps, r)
+  auto round_sk = [&](const TTView &v, double eps, int r) -> hipError_t {
+    hipError_t e = hipSuccess;
+    if (o->sketch > 0) e = sketch_tt(v, r + o->sketch, o->seed, call++, L.sk_ws, s);
+    if (e != hipSuccess) return e;
+    return round_tt(v, eps, r, rw, s, o->sketch > 0, o->sketch > 0 ? r + o->sketch : 0);
+  };
+  auto read_scalar = [&](int idx, double &out) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(&out, sc + idx, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+  };
+  if (o->method == QTT_SOLVE_CHEBYSHEV && fnorm > 0.0) {
+    const int rin = o->rmax_in;
+    // <f, C f> with f rounded to the inner rank cap (exact when f's ranks fit)
+    QTT_HIP(launch_copy_tt(fv, L.R.v, s));
+    QTT_HIP(round_tt(L.R.v, 0.0, rin, rw, s));
+    QTT_HIP(launch_dot3(L.Rin, Cv, L.Rin, sc + S_RHO, L.dot_ws, L.dot_elems, s));
+    double fcf = 0.0;
+    QTT_HIP(read_scalar(S_RHO, fcf));
+    if (!(fcf > 0.0)) return fail(QTT_E_INVAL, "<f, C f> is not positive: C is not SPD");
+    const double lmin = o->lmin > 0.0 ? o->lmin : 0.09;
+    double lmax = o->lmax;
+    if (!(lmax > 0.0)) {
+      // power steps v <- round(C round(K v)); Rayleigh quotient
+      // <K v, C K v> / <v, K v> (no normalisation: the rounding is relative
+      // and 12 steps stay far inside the FP64 range)
+      QTT_HIP(launch_copy_tt(L.R.v, L.Pp[0].v, s));
+      for (int it = 0; it < 12; ++it) {
+        QTT_HIP(launch_dot3(L.Pin, Kv, L.Pin, sc + S_PK, L.dot_ws, L.dot_elems, s));
+        QTT_HIP(launch_matvec(Kv, L.Pp[0].v, L.Ku.v, lowp, s));
+        QTT_HIP(launch_copy_tt(L.Ku.v, L.R.v, s));
+        QTT_HIP(round_sk(L.R.v, o->eps_in, rin));
+        QTT_HIP(launch_dot3(L.Rin, Cv, L.Rin, sc + S_CR, L.dot_ws, L.dot_elems, s));
+        QTT_HIP(launch_matvec(Cv, L.R.v, L.Q.v, lowp, s));
+        QTT_HIP(launch_copy_tt(L.Q.v, L.Pp[0].v, s));
+        QTT_HIP(round_sk(L.Pp[0].v, o->eps_in, rin));
+      }
+      double pk = 0.0, cr = 0.0;
+      QTT_HIP(read_scalar(S_PK, pk));
+      QTT_HIP(read_scalar(S_CR, cr));
+      if (!(pk > 0.0) || !std::isfinite(cr)) return fail(QTT_E_INVAL, "K is not SPD (power step)");
+      lmax = 1.12 * cr / pk;
+      if (!(lmax > lmin)) lmax = 2.0 * lmin;
+      if (trace) std::fprintf(stderr, "[qtt_solve] %.3fs lmax estimate %.4f\n", secs(), lmax);
+    }
+    R.lmax = lmax;
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+    const double sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    int pi = 0, nh = 0;
+    bool have_d = false;
+    int it = 0;
+    for (it = 0; it <= o->maxit_in; ++it) {
+      // r = round(f - K u): exact product and difference, then rounding
+      // relative to ||r||
+      if (have_u) {
+        QTT_HIP(launch_matvec(Kv, L.U[cur].v, L.Ku.v, lowp, s));
+        QTT_HIP(launch_axpby(1.0, nullptr, fv, -1.0, nullptr, L.Ku.v, L.R.v, s));
+      } else {
+        QTT_HIP(launch_copy_tt(fv, L.R.v, s));
+      }
+      QTT_HIP(round_sk(L.R.v, o->eps_in, rin));
+      // the criterion <r, C r>, then C r
+      QTT_HIP(launch_dot3(L.Rin, Cv, L.Rin, sc + S_RES, L.dot_ws, L.dot_elems, s));
+      QTT_HIP(launch_matvec(Cv, L.R.v, L.Q.v, lowp, s));
+      if (it % o->check_every == 0 || it == o->maxit_in) {
+        double rcr = 0.0;
+        QTT_HIP(read_scalar(S_RES, rcr));
+        if (!std::isfinite(rcr)) return fail(QTT_E_NOCONV, "residual is not finite");
+        const double crit = std::sqrt(std::fmax(rcr, 0.0) / fcf);
+        if (nh < 64) R.residual_hist[nh] = crit;
+        ++nh;
+        R.criterion = crit;
+        if (trace)
+          std::fprintf(stderr, "[qtt_solve] %.3fs it %d criterion %.3e\n", secs(), it, crit);
+        if (crit <= o->tol) {
+          converged = true;
+          break;
+        }
+      }
+      if (it == o->maxit_in) break;
+      // z = round(C r); d = c1 d + c2 z
+      QTT_HIP(round_sk(L.Q.v, o->eps_in, rin));
+      if (!have_d) {
+        QTT_HIP(launch_copy_tt(L.Q.v, L.Pp[pi].v, s));
+        QTT_HIP(launch_scale(L.Pp[pi].v, 1.0 / theta, s));
+        have_d = true;
+      } else {
+        const double rho_new = 1.0 / (2.0 * sigma - rho);
+        QTT_HIP(launch_axpby(rho_new * rho, nullptr, L.Pp[pi].v, 2.0 * rho_new / delta, nullptr,
+                             L.Q.v, L.Pp[1 - pi].v, s));
+        pi = 1 - pi;
+        QTT_HIP(round_tt(L.Pp[pi].v, o->eps_in, rin, rw, s, false, 2 * rin));
+        rho = rho_new;
+      }
+      // u = round(u + d)
+      if (have_u) {
+        QTT_HIP(launch_axpby(1.0, nullptr, L.U[cur].v, 1.0, nullptr, L.Pp[pi].v, L.U[1 - cur].v,
+                             s));
+        cur = 1 - cur;
+        QTT_HIP(round_tt(L.U[cur].v, o->eps, o->rmax, rw, s, false, o->rmax + rin));
+      } else {
+        QTT_HIP(launch_copy_tt(L.Pp[pi].v, L.U[cur].v, s));
+        have_u = true;
+      }
+    }
+    R.inner = it;
+    // FP64 check of the returned iterate
+    if (have_u) {
+      double rel = 0.0;
+      QTT_HIP(launch_matvec(Kv, L.U[cur].v, L.Ku.v, QTT_F64, s));
+      QTT_HIP(launch_axpby(1.0, nullptr, fv, -1.0, nullptr, L.Ku.v, L.R.v, s));
+      int32_t ur[QTT_MAXD + 1];
+      std::vector<int32_t> rr(D + 1);
+      QTT_HIP(hipMemcpyAsync(ur, L.U[cur].v.rk, sizeof(int32_t) * (D + 1), hipMemcpyDeviceToHost,
+                             s));
+      QTT_HIP(hipStreamSynchronize(s));
+      for (int k = 0; k <= D; ++k) {
+        rr[k] = (k == 0 || k == D) ? 1 : f->ranks[k] + K->ranks[k] * ur[k];
+        if (ur[k] < 1 || ur[k] > L.U[cur].v.cap[k] || rr[k] > L.R.v.cap[k])
+          return fail(QTT_E_CAPACITY, "iterate rank exceeds its buffer");
+      }
+      QTT_HIP(tt_full(L.R.v, rr.data(), L.dense, L.full_ws, s));
+      QTT_HIP(launch_diff_norm2(L.dense, nullptr, L.N, sc + S_RES, s));
+      double rn2[2];
+      QTT_HIP(hipMemcpyAsync(rn2, sc + S_RES, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+      QTT_HIP(hipStreamSynchronize(s));
+      rel = std::sqrt(rn2[0]) / fnorm;
+      R.residual = rel;
+    }
+  }
+  for (int out = 0; out <= o->maxit_out && fnorm > 0.0 && o->method == QTT_SOLVE_CG_IR; ++out) {
     // residual r = f - K u (exact product and difference)
     if (have_u) {
       QTT_HIP(launch_matvec(Kv, L.U[cur].v, L.Ku.v, QTT_F64, s));
@@ -328,7 +496,8 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
     if (out == o->maxit_out) break;
     // the correction's right-hand side: the residual rounded to (eps_in, rmax_in)
     if (o->sketch > 0) QTT_HIP(sketch_tt(L.R.v, o->rmax_in + o->sketch, o->seed, call++, L.sk_ws, s));
-    QTT_HIP(round_tt(L.R.v, o->eps_in, o->rmax_in, rw, s));
+    QTT_HIP(round_tt(L.R.v, o->eps_in, o->rmax_in, rw, s, o->sketch > 0,
+                     o->sketch > 0 ? o->rmax_in + o->sketch : 0));
     double nr[2];
     QTT_HIP(hipMemcpyAsync(nr, rw.scal, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
     QTT_HIP(hipStreamSynchronize(s));
@@ -345,7 +514,8 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
       hipError_t e = hipSuccess;
       if (o->sketch > 0) e = sketch_tt(v, o->rmax_in + o->sketch, o->seed, call++, L.sk_ws, s);
       if (e != hipSuccess) return e;
-      return round_tt(v, o->eps_in, o->rmax_in, rw, s);
+      return round_tt(v, o->eps_in, o->rmax_in, rw, s, o->sketch > 0,
+                      o->sketch > 0 ? o->rmax_in + o->sketch : 0);
     };
     if (pre) {
       // z = C r (exact), rho = <r, z>, p = round(z)
@@ -369,7 +539,7 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
       // reaches the true residual multiplied by ||K||
       QTT_HIP(launch_axpby(1.0, nullptr, L.X[xi].v, 1.0, sc + S_ALPHA, L.Pp[pi].v, L.X[1 - xi].v, s));
       xi = 1 - xi;
-      QTT_HIP(round_tt(L.X[xi].v, o->eps, o->rmax, rw, s));
+      QTT_HIP(round_tt(L.X[xi].v, o->eps, o->rmax, rw, s, false, o->rmax + o->rmax_in));
       // r = round(r - alpha q), rounded as one sum; ||r||^2 from the rounding
       QTT_HIP(launch_axpby(1.0, nullptr, L.Rr[ri].v, -1.0, sc + S_ALPHA, L.Q.v, L.Rr[1 - ri].v, s));
       ri = 1 - ri;
@@ -410,7 +580,7 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
       QTT_HIP(launch_copy_tt(L.X[xi].v, L.U[cur].v, s));
       have_u = true;
     }
-    QTT_HIP(round_tt(L.U[cur].v, o->eps, o->rmax, rw, s));
+    QTT_HIP(round_tt(L.U[cur].v, o->eps, o->rmax, rw, s, false, 2 * o->rmax));
     R.outer += 1;
   }
   if (!have_u) {
