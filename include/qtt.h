@@ -186,13 +186,16 @@ qtt_status qtt_axpby(double a, const qtt_tt *x, double b, const qtt_tt *y,
 /* ------------------------------------------------------------ solve   */
 typedef enum {
   QTT_SOLVE_CG_IR = 0,     /* truncated CG with FP64 iterative refinement      */
-  QTT_SOLVE_CHEBYSHEV = 1  /* preconditioned Chebyshev iteration, true residual
+  QTT_SOLVE_CHEBYSHEV = 1, /* preconditioned Chebyshev iteration, true residual
                               every step (needs `precond`)                      */
+  QTT_SOLVE_FCG = 2        /* flexible preconditioned CG (one stored direction),
+                              true residual every step, exact step length
+                              (needs `precond`)                                */
 } qtt_solve_method;
 
 typedef struct {
   double tol;        /* CG_IR: stop when ||f - K u|| <= tol ||f|| (FP64).
-                        CHEBYSHEV: stop when sqrt(<r, C r>) <= tol sqrt(<f, C f>)
+                        CHEBYSHEV, FCG: stop when sqrt(<r, C r>) <= tol sqrt(<f, C f>)
                         with r = f - K u: the preconditioned residual, equal to
                         the relative energy-norm error within sqrt(lmax/lmin) */
   double eps;        /* rounding accuracy of the iterate u                    */
@@ -203,7 +206,7 @@ typedef struct {
   int32_t rmax_in;   /* rank cap of those vectors (<= rmax for CHEBYSHEV)    */
   double red_in;     /* CG_IR: residual reduction of each correction solve   */
   int32_t maxit_in;  /* CG_IR: CG iterations per correction solve;
-                        CHEBYSHEV: iterations in total                        */
+                        CHEBYSHEV, FCG: iterations in total                   */
   int32_t maxit_out; /* CG_IR: refinement steps                              */
   int32_t check_every; /* iterations between host convergence checks        */
   qtt_dtype compute; /* contractions: QTT_F64, QTT_F32 or QTT_BF16 (QR, SVD,
@@ -241,6 +244,12 @@ typedef struct {
  * difference), checks its FP64 norm and rounds it; the inner loop runs
  * truncated (P)CG on K e = r with its vectors rounded to (eps_in, rmax_in);
  * u <- round(u + e, eps, rmax).
+ * FCG: z = round(C r), p = round(z - beta p) with beta = <z, K p>/<p, K p>,
+ * u = round(u + alpha p) with alpha = <f - K u, p>/<p, K p> evaluated from u
+ * and p themselves (three-operand inner products, no product formed), so
+ * the energy error decreases at every step whatever the truncation of z and
+ * p (Notay's flexible CG with one stored direction); r = round(f - K u) is
+ * recomputed from the iterate; stop as CHEBYSHEV.
  * CHEBYSHEV: u_{k+1} = u_k + d_k with d_k = c1 d_{k-1} + c2 round(C r_k),
  * r_k = round(f - K u_k) recomputed from u_k at every step (so rounding
  * errors do not accumulate in a recurrence), c1, c2 from the Chebyshev

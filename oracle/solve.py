@@ -180,3 +180,49 @@ def chebyshev(K, f, C, opts: ChebOpts, x0=None):
     if x is None:
         x = _zero_like(f)
     return x, rep
+
+
+def fcg(K, f, C, opts: ChebOpts, x0=None):
+    """Flexible preconditioned CG with one stored direction and the true
+    residual every step (Notay, SIAM J. Sci. Comput. 2000, with m = 1):
+        alpha = <f - K x, p> / <p, K p>,  x = round(x + alpha p),
+        r = round(f - K x),  z = round(C r),
+        beta = <z, K p> / <p, K p>,  p = round(z - beta p).
+    alpha is the exact energy minimiser along the direction actually used
+    (computed from x and p, not from the rounded r), so the energy error
+    decreases at every step whatever the truncation of z and p.  Stop as in
+    chebyshev().  lmin and lmax are not used."""
+    rep = SolveReport()
+    Cf = T.matvec(C, f)
+    fCf = T.dot(f, Cf)
+    x = x0
+    p = None
+    for it in range(opts.maxit + 1):
+        if x is None:
+            r = T.tt_round(f, opts.eps_r, opts.rmax_r)
+        else:
+            r = T.tt_round(T.add(f, T.matvec(K, x), coeffs=[1.0, -1.0]), opts.eps_r, opts.rmax_r)
+        Cr = T.matvec(C, r)
+        rel = math.sqrt(max(T.dot(r, Cr), 0.0) / fCf)
+        rep.residuals.append(rel)
+        if rel <= opts.tol:
+            rep.converged = True
+            break
+        if it == opts.maxit:
+            break
+        z = T.tt_round(Cr, opts.eps_d, opts.rmax_d)
+        if p is None:
+            p = z
+        else:
+            beta = T.dot(z, T.matvec(K, p)) / pKp
+            p = T.tt_round(T.add(z, p, coeffs=[1.0, -beta]), opts.eps_d, opts.rmax_d)
+        Kp = T.matvec(K, p)
+        pKp = T.dot(p, Kp)
+        fp = T.dot(f, p) - (0.0 if x is None else T.dot(x, Kp))
+        alpha = fp / pKp
+        x = T.scale(p, alpha) if x is None else T.tt_round(T.add(x, p, coeffs=[1.0, alpha]),
+                                                           opts.eps, opts.rmax)
+        rep.inner += 1
+    if x is None:
+        x = _zero_like(f)
+    return x, rep

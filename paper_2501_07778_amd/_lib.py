@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libqtt.so")
 
 QTT_F64, QTT_F32, QTT_BF16 = 0, 1, 2
 _DTYPES = {"f64": QTT_F64, "f32": QTT_F32, "bf16": QTT_BF16}
-_METHODS = {"cg": 0, "chebyshev": 1}
+_METHODS = {"cg": 0, "chebyshev": 1, "fcg": 2}
 MAX_CORES = 40
 
 
@@ -348,7 +348,7 @@ class SolveOpts:
     sketch: int = 0
     seed: int = 0
     precond: Optional["TT"] = None
-    method: str = "cg"          # "cg" (CG with refinement) or "chebyshev"
+    method: str = "cg"          # "cg" (CG with refinement), "chebyshev" or "fcg"
     lmin: float = 0.0
     lmax: float = 0.0
 

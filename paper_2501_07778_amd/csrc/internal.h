@@ -99,8 +99,8 @@ hipError_t launch_copy_tt(const TTView &src, const TTView &dst,
 hipError_t launch_axpby(double a, const double *a_dev, const TTView &x,
                         double b, const double *b_dev, const TTView &y,
                         const TTView &z, hipStream_t s);
-// v <- c v (the first core is scaled)
-hipError_t launch_scale(const TTView &v, double c, hipStream_t s);
+// v <- c v (the first core is scaled); c_dev (may be NULL) multiplies c
+hipError_t launch_scale(const TTView &v, double c, hipStream_t s, const double *c_dev = nullptr);
 // <x, y> into *out (device), workspace of `ws_elems` doubles
 hipError_t launch_dot(const TTView &x, const TTView &y, double *out,
                       double *ws, int64_t ws_elems, hipStream_t s);
@@ -119,7 +119,8 @@ enum ScalarOp {
   SC_SQRT_DIV = 3,   // s0 = sqrt(max(s1,0)) / c
   SC_SET = 4,        // s0 = c
   SC_DIV_POS = 5,    // s0 = s2 > 0 ? s1 / s2 : 0
-  SC_NORM2 = 6       // s0 = s1[0]^2 - s1[1] (squared norm after truncation)
+  SC_NORM2 = 6,      // s0 = s1[0]^2 - s1[1] (squared norm after truncation)
+  SC_DIFF_DIV = 7    // s0 = s2[0] > 0 ? (s1[0] - s1[1]) / s2[0] : 0
 };
 
 // rounding (exact algorithm); ws sized by round_workspace_elems

@@ -322,8 +322,9 @@ __global__ void __launch_bounds__(DOT_THREADS)
 }
 
 // core 0 of a TT vector times c (ranks from the device)
-__global__ void k_scale_first(TTView v, double c) {
+__global__ void k_scale_first(TTView v, double c, const double *c_dev) {
   if (v.rk[1] > v.cap[1]) return;
+  if (c_dev) c *= *c_dev;
   const int64_t ne = (int64_t)v.n[0] * v.m[0] * v.rk[1];
   double *c0 = v.data + v.off[0];
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
@@ -341,6 +342,7 @@ __global__ void k_scalar(int op, double *s0, const double *s1,
     case SC_SET: *s0 = c; break;
     case SC_DIV_POS: *s0 = (*s2 > 0.0) ? *s1 / *s2 : 0.0; break;
     case SC_NORM2: *s0 = fmax(s1[0] * s1[0] - s1[1], 0.0); break;
+    case SC_DIFF_DIV: *s0 = (s2[0] > 0.0) ? (s1[0] - s1[1]) / s2[0] : 0.0; break;
   }
 }
 
@@ -364,10 +366,10 @@ int64_t max_core_cap(const TTView &v) {
 
 }  // namespace
 
-hipError_t launch_scale(const TTView &v, double c, hipStream_t s) {
+hipError_t launch_scale(const TTView &v, double c, hipStream_t s, const double *c_dev) {
   const int64_t ne = (int64_t)v.n[0] * v.m[0] * v.cap[1];
   const int blocks = (int)std::min<int64_t>((ne + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_scale_first, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, v, c);
+  hipLaunchKernelGGL(k_scale_first, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, v, c, c_dev);
   return hipGetLastError();
 }
 

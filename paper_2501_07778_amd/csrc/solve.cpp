@@ -46,7 +46,9 @@ namespace {
 
 struct SolveLayout {
   TTDesc U[2], Ku, R, X[2], Rr[2], Pp[2], Q;
-  TTView Rin, Pin;  // R and Pp[0] with the caps of a rounded inner vector
+  TTView Rin, Pin, Qin;  // R, Pp[0], Q with the caps of a rounded inner vector
+  TTView Pin1;           // Pp[1] likewise
+  TTView Uin[2];         // U[s] with the caps of a rounded iterate
   RoundWs rw;
   double *dot_ws = nullptr;
   int64_t dot_elems = 0;
@@ -59,7 +61,7 @@ struct SolveLayout {
 
 enum {
   S_FNORM2 = 0, S_RHO, S_PQ, S_ALPHA, S_BETA, S_RHONEW, S_ONE, S_RES, S_PK, S_CR,
-  S_COUNT = 16
+  S_FP, S_XKP, S_ZKP, S_PKP, S_COUNT = 16
 };
 
 std::vector<int> caps_for(const qtt_tt *K, int r) {
@@ -130,13 +132,20 @@ bool carve(Arena &ar, const qtt_tt *K, const qtt_tt *f, const qtt_solve_opts *o,
   {
     L.Rin = L.R.v;
     L.Pin = L.Pp[0].v;
+    L.Pin1 = L.Pp[1].v;
+    L.Qin = L.Q.v;
     TTView Kc = L.R.v, Cc = L.R.v;
     for (int k = 0; k <= D; ++k) {
-      L.Rin.cap[k] = L.Pin.cap[k] = ci[k];
+      L.Rin.cap[k] = L.Pin.cap[k] = L.Pin1.cap[k] = L.Qin.cap[k] = ci[k];
       Kc.cap[k] = K->ranks[k];
       Cc.cap[k] = o->precond ? o->precond->ranks[k] : 1;
     }
-    for (int64_t e : {dot3_ws_elems(L.Rin, Cc, L.Rin), dot3_ws_elems(L.Pin, Kc, L.Pin)})
+    L.Uin[0] = L.U[0].v;
+    L.Uin[1] = L.U[1].v;
+    for (int k = 0; k <= D; ++k) L.Uin[0].cap[k] = L.Uin[1].cap[k] = cu[k];
+    const TTView &Uc = L.Uin[0];
+    for (int64_t e : {dot3_ws_elems(L.Rin, Cc, L.Rin), dot3_ws_elems(L.Pin, Kc, L.Pin),
+                      dot3_ws_elems(Uc, Kc, L.Pin), dot_ws_elems(fv, L.Pin)})
       L.dot_elems = e > L.dot_elems ? e : L.dot_elems;
   }
   L.dot_ws = (double *)ar.take(sizeof(double) * L.dot_elems);
@@ -188,11 +197,12 @@ qtt_status check_opts(const qtt_solve_opts *o) {
   if (o->compute != QTT_F64 && o->compute != QTT_F32 && o->compute != QTT_BF16)
     return fail(QTT_E_INVAL, "bad compute dtype");
   if (o->sketch < 0 || o->sketch > 256) return fail(QTT_E_INVAL, "sketch must be in 0..256");
-  if (o->method != QTT_SOLVE_CG_IR && o->method != QTT_SOLVE_CHEBYSHEV)
+  if (o->method != QTT_SOLVE_CG_IR && o->method != QTT_SOLVE_CHEBYSHEV &&
+      o->method != QTT_SOLVE_FCG)
     return fail(QTT_E_INVAL, "unknown solve method");
-  if (o->method == QTT_SOLVE_CHEBYSHEV) {
-    if (!o->precond) return fail(QTT_E_INVAL, "the Chebyshev solve needs a preconditioner");
-    if (o->rmax_in > o->rmax) return fail(QTT_E_INVAL, "Chebyshev solve: rmax_in must be <= rmax");
+  if (o->method != QTT_SOLVE_CG_IR) {
+    if (!o->precond) return fail(QTT_E_INVAL, "this solve method needs a preconditioner");
+    if (o->rmax_in > o->rmax) return fail(QTT_E_INVAL, "rmax_in must be <= rmax");
     if (o->check_every < 1) return fail(QTT_E_INVAL, "check_every must be >= 1");
     const double lmin = o->lmin > 0.0 ? o->lmin : 0.09;
     if (o->lmax > 0.0 && !(o->lmax > lmin))
@@ -330,7 +340,8 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(s);
   };
-  if (o->method == QTT_SOLVE_CHEBYSHEV && fnorm > 0.0) {
+  if (o->method != QTT_SOLVE_CG_IR && fnorm > 0.0) {
+    const bool cheb = o->method == QTT_SOLVE_CHEBYSHEV;
     const int rin = o->rmax_in;
     // <f, C f> with f rounded to the inner rank cap (exact when f's ranks fit)
     QTT_HIP(launch_copy_tt(fv, L.R.v, s));
@@ -341,7 +352,7 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
     if (!(fcf > 0.0)) return fail(QTT_E_INVAL, "<f, C f> is not positive: C is not SPD");
     const double lmin = o->lmin > 0.0 ? o->lmin : 0.09;
     double lmax = o->lmax;
-    if (!(lmax > 0.0)) {
+    if (cheb && !(lmax > 0.0)) {
       // power steps v <- round(C round(K v)); Rayleigh quotient
       // <K v, C K v> / <v, K v> (no normalisation: the rounding is relative
       // and 12 steps stay far inside the FP64 range)
@@ -364,7 +375,7 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
       if (!(lmax > lmin)) lmax = 2.0 * lmin;
       if (trace) std::fprintf(stderr, "[qtt_solve] %.3fs lmax estimate %.4f\n", secs(), lmax);
     }
-    R.lmax = lmax;
+    R.lmax = cheb ? lmax : 0.0;
     const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
     const double sigma = theta / delta;
     double rho = 1.0 / sigma;
@@ -400,8 +411,44 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
         }
       }
       if (it == o->maxit_in) break;
-      // z = round(C r); d = c1 d + c2 z
+      // z = round(C r)
       QTT_HIP(round_sk(L.Q.v, o->eps_in, rin));
+      if (!cheb) {
+        // p = round(z - beta p), beta = <z, K p> / <p, K p>
+        if (!have_d) {
+          QTT_HIP(launch_copy_tt(L.Q.v, L.Pp[pi].v, s));
+          have_d = true;
+        } else {
+          QTT_HIP(launch_dot3(L.Qin, Kv, pi == 0 ? L.Pin : L.Pin1, sc + S_ZKP, L.dot_ws,
+                              L.dot_elems, s));
+          QTT_HIP(launch_scalar(SC_DIV_POS, sc + S_BETA, sc + S_ZKP, sc + S_PKP, 0.0, s));
+          QTT_HIP(launch_axpby(1.0, nullptr, L.Q.v, -1.0, sc + S_BETA, L.Pp[pi].v,
+                               L.Pp[1 - pi].v, s));
+          pi = 1 - pi;
+          QTT_HIP(round_tt(L.Pp[pi].v, o->eps_in, rin, rw, s, false, 2 * rin));
+        }
+        // alpha = <f - K u, p> / <p, K p> from u and p themselves
+        const TTView &pv = pi == 0 ? L.Pin : L.Pin1;
+        QTT_HIP(launch_dot3(pv, Kv, pv, sc + S_PKP, L.dot_ws, L.dot_elems, s));
+        QTT_HIP(launch_dot(fv, pv, sc + S_FP, L.dot_ws, L.dot_elems, s));
+        if (have_u)
+          QTT_HIP(launch_dot3(L.Uin[cur], Kv, pv, sc + S_XKP, L.dot_ws, L.dot_elems, s));
+        else
+          QTT_HIP(launch_scalar(SC_SET, sc + S_XKP, nullptr, nullptr, 0.0, s));
+        QTT_HIP(launch_scalar(SC_DIFF_DIV, sc + S_ALPHA, sc + S_FP, sc + S_PKP, 0.0, s));
+        if (have_u) {
+          QTT_HIP(launch_axpby(1.0, nullptr, L.U[cur].v, 1.0, sc + S_ALPHA, L.Pp[pi].v,
+                               L.U[1 - cur].v, s));
+          cur = 1 - cur;
+          QTT_HIP(round_tt(L.U[cur].v, o->eps, o->rmax, rw, s, false, o->rmax + rin));
+        } else {
+          QTT_HIP(launch_copy_tt(L.Pp[pi].v, L.U[cur].v, s));
+          QTT_HIP(launch_scale(L.U[cur].v, 1.0, s, sc + S_ALPHA));
+          have_u = true;
+        }
+        continue;
+      }
+      // Chebyshev: d = c1 d + c2 z
       if (!have_d) {
         QTT_HIP(launch_copy_tt(L.Q.v, L.Pp[pi].v, s));
         QTT_HIP(launch_scale(L.Pp[pi].v, 1.0 / theta, s));

@@ -8,6 +8,7 @@ import pytest
 import workloads as W
 from oracle import assembly as A
 from oracle import fem
+from oracle import precond as PC
 from oracle import qtt as T
 
 pytestmark = pytest.mark.gpu
@@ -169,3 +170,43 @@ def test_pcg_sketched_solve_matches_direct(P, d):
     Ks, fs, _, _ = fem.assemble_system(prob)
     r = fem.permute_matrix_to_qtt(Ks, d) @ ud - fem.to_qtt_order(fs, d)
     assert np.linalg.norm(r) / np.linalg.norm(fs) == pytest.approx(rep["residual"], rel=1e-3)
+
+
+@pytest.mark.parametrize("method", ["chebyshev", "fcg"])
+@pytest.mark.parametrize("d,rin,sketch", [(3, 16, 0), (4, 16, 0), (5, 32, 8)])
+def test_bpx_solves_match_direct(P, d, rin, sketch, method):
+    """BPX-preconditioned Chebyshev solve (true residual every step): the
+    solution matches the sparse direct solve; the spectral bound estimated
+    on the device lies above the dense spectrum of C K; the reported FP64
+    residual equals the oracle's residual of the returned iterate."""
+    prob = W.cantilever_traction(d)
+    uref, _ = fem.solve_problem(prob)
+    K, f = P.assemble(prob)
+    C = P.assemble_bpx(prob)
+    opts = P.SolveOpts(tol=1e-9, eps=1e-11, rmax=64, eps_in=1e-3, rmax_in=rin, maxit_in=400,
+                       check_every=5, precond=C, sketch=sketch, seed=5, method=method)
+    u, rep = P.solve(K, f, opts)
+    ud = T.full_vector(P.tt_to_cores(u))
+    err = np.linalg.norm(ud - uref) / np.linalg.norm(uref)
+    assert rep["status"] == 0 and err <= 1e-8, (err, rep)
+    assert rep["criterion"] <= 1e-9
+    Ks, fs, mask, info = fem.assemble_system(prob)
+    if d <= 4 and method == "chebyshev":
+        Cd = PC.bpx_dense(prob, info["gamma_D"])
+        Lc = np.linalg.cholesky(Cd)
+        lmax = np.linalg.eigvalsh(Lc.T @ Ks.toarray() @ Lc).max()
+        assert lmax < rep["lmax"] < 1.3 * lmax
+    r = fem.permute_matrix_to_qtt(Ks, d) @ ud - fem.to_qtt_order(fs, d)
+    assert np.linalg.norm(r) / np.linalg.norm(fs) == pytest.approx(rep["residual"], rel=1e-6)
+
+
+def test_bpx_solves_reject_bad_options(P):
+    prob = W.cantilever_traction(2)
+    K, f = P.assemble(prob)
+    with pytest.raises(P.QttError):
+        P.solve(K, f, P.SolveOpts(method="chebyshev"))           # no preconditioner
+    C = P.assemble_bpx(prob)
+    with pytest.raises(P.QttError):
+        P.solve(K, f, P.SolveOpts(method="chebyshev", precond=C, rmax=16, rmax_in=32))
+    with pytest.raises(P.QttError):
+        P.solve(K, f, P.SolveOpts(method="fcg"))                 # no preconditioner

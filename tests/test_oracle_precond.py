@@ -62,6 +62,8 @@ def test_bpx_condition_numbers():
         assert np.linalg.eigvalsh(Cd).min() > 0
         L = np.linalg.cholesky(Cd)
         ev = np.linalg.eigvalsh(L.T @ Kd @ L)
+        # the default lower spectral bound of the Chebyshev solve
+        assert ev.min() > 0.09
         kc.append(ev.max() / ev.min())
         kk.append(np.linalg.cond(Kd))
     assert kk[2] / kk[1] > 3.5 and kk[1] / kk[0] > 3.5      # K: x4 per level
@@ -82,3 +84,27 @@ def test_oracle_pcg_solve_matches_direct(d):
     u0, rep0 = S.solve(Kq, fq, S.SolveOpts(tol=1e-10, eps=1e-11, eps_in=1e-3, red_in=1e-3,
                                            rmax_in=32))
     assert rep.inner < rep0.inner
+
+
+@pytest.mark.parametrize("d", [3, 4])
+def test_oracle_chebyshev_matches_direct(d):
+    """Chebyshev iteration on C K u = C f with the true residual every step:
+    the energy-type stop at tol gives the direct solution to about tol."""
+    prob = W.cantilever_traction(d)
+    K, f, mask, info = fem.assemble_system(prob)
+    Kq, fq = A.assemble_qtt(prob)
+    Cq = PC.bpx_qtt(prob, info["gamma_D"])
+    uref, _ = fem.solve_problem(prob)
+    Cd = PC.bpx_dense(prob, info["gamma_D"])
+    Lc = np.linalg.cholesky(Cd)
+    ev = np.linalg.eigvalsh(Lc.T @ K.toarray() @ Lc)
+    o = S.ChebOpts(tol=1e-9, eps=1e-12, eps_r=1e-3, eps_d=1e-3, lmin=0.09, lmax=1.05 * ev.max())
+    u, rep = S.chebyshev(Kq, fq, Cq, o)
+    assert rep.converged
+    err = np.linalg.norm(T.full_vector(u) - uref) / np.linalg.norm(uref)
+    assert err <= 1e-8
+    # an upper bound below the spectrum makes the same iteration diverge
+    o.lmax = 0.5 * ev.max()
+    o.maxit = 60
+    _, rep_bad = S.chebyshev(Kq, fq, Cq, o)
+    assert not rep_bad.converged and rep_bad.residuals[-1] > 1.0
