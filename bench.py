@@ -8,9 +8,10 @@ to 25) is assembled on the device before the timed region; the vector x is
 a seeded rank-64 train (the rank cap of the solve at this level) with
 Gaussian cores.  One step is the hot path of every solver iteration:
 
-    y = K x                       qtt_matvec, FP64, ranks 25*64 = 1600
-    y <- round(y, 1e-8, 64)       qtt_round_sketch: Gaussian sketch of rank
-                                  72, then the exact rounding
+    y = round(K x, 1e-8, 64)      qtt_matvec_round: the FP64 product (ranks
+                                  25*64 = 1600) formed in the workspace, a
+                                  Gaussian sketch of rank 72, then the exact
+                                  rounding of the sketch
 
 The value is the algorithmic HBM traffic of a step (read K and x, write the
 product, read it back once in the rounding, write the result) divided by the
@@ -60,9 +61,8 @@ def workload(level: int):
     return prob, K, x
 
 
-def step(P, K, x, y, seed, compute="f64"):
-    y = P.matvec(K, x, compute, y=y)
-    P.round_sketch(y, ELL, seed, EPS, RANK)
+def step(P, K, x, y, ws, seed, compute="f64"):
+    y, _, _ = P.matvec_round(K, x, ELL, seed, EPS, RANK, compute, y=y, ws=ws)
     return y
 
 
@@ -145,18 +145,19 @@ def main():
 
     prob, K, x = workload(args.level)
     y = None
+    ws = P.matvec_round_workspace(K, x, ELL)
     for i in range(args.warmup):
-        y = step(P, K, x, y, 1000 + i)
+        y = step(P, K, x, y, ws, 1000 + i)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        y = step(P, K, x, y, i)
+        y = step(P, K, x, y, ws, i)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     # algorithmic bytes: read K, x; write Y; read Y once; write the result
-    yfull = P.matvec(K, x)
-    nbytes = tt_bytes(K) + tt_bytes(x) + 2 * tt_bytes(yfull) + tt_bytes(y)
-    del yfull
+    prod = 8 * sum(K.ranks[k] * x.ranks[k] * K.nrow[k] * K.ranks[k + 1] * x.ranks[k + 1]
+                   for k in range(K.D))
+    nbytes = tt_bytes(K) + tt_bytes(x) + 2 * prod + tt_bytes(y)
     value = nbytes / dt / 1e9
     roof = matvec_roofline(P, torch, K, x)
     line = {

@@ -171,6 +171,19 @@ qtt_status qtt_round_sketch(qtt_tt *x, int32_t ell, uint64_t seed, double eps, i
 /* Workspace bytes of qtt_round_sketch for x's current ranks and `ell`.    */
 qtt_status qtt_round_sketch_workspace(const qtt_tt *x, int32_t ell, size_t *bytes);
 
+/* qtt_matvec_round — the hot step of every solver iteration in one call:
+ * y = round(A x), the product formed in the workspace (never in y) and
+ * rounded in place there: with ell > 0 by a Gaussian sketch of rank ell
+ * (as qtt_round_sketch), then the exact rounding to (eps, rmax); with
+ * ell = 0 by the exact rounding alone.  y receives the rounded train
+ * (capacity for ranks min(rmax, ...) is enough) and its ranks; *norm and
+ * *err as qtt_round.  compute as qtt_matvec.  Synchronises `stream`.      */
+qtt_status qtt_matvec_round(const qtt_tt *A, const qtt_tt *x, qtt_tt *y, qtt_dtype compute,
+                            int32_t ell, uint64_t seed, double eps, int32_t rmax, double *norm,
+                            double *err, void *ws, size_t ws_bytes, void *stream);
+qtt_status qtt_matvec_round_workspace(const qtt_tt *A, const qtt_tt *x, int32_t ell,
+                                      size_t *bytes);
+
 /* qtt_dot — <x, y> of two TT vectors of equal modes (left-to-right
  * environment sweep).  Synchronises `stream`.                              */
 qtt_status qtt_dot(const qtt_tt *x, const qtt_tt *y, double *out, void *ws,

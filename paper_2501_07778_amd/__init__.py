@@ -7,6 +7,6 @@ package loads the library and fails loudly when it is missing.
 """
 from ._lib import (  # noqa: F401
     LIB_PATH, QttError, TT, Problem, SolveOpts, lib, load_library,
-    matvec, round_, round_sketch, dot, axpby, assemble, assemble_bpx, solve, solve_workspace_bytes,
+    matvec, matvec_round, matvec_round_workspace, round_, round_sketch, dot, axpby, assemble, assemble_bpx, solve, solve_workspace_bytes,
     tt_from_cores, tt_to_cores, problem_from_workload, version,
 )

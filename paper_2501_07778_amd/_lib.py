@@ -84,6 +84,10 @@ def load_library(path: str = LIB_PATH):
     L.qtt_round_sketch.argtypes = [P(_TT), C.c_int32, C.c_uint64, C.c_double, C.c_int32,
                                    P(C.c_double), P(C.c_double), vp, sz, vp]
     L.qtt_round_sketch_workspace.argtypes = [P(_TT), C.c_int32, P(sz)]
+    L.qtt_matvec_round.argtypes = [P(_TT), P(_TT), P(_TT), C.c_int, C.c_int32, C.c_uint64,
+                                   C.c_double, C.c_int32, P(C.c_double), P(C.c_double), vp, sz,
+                                   vp]
+    L.qtt_matvec_round_workspace.argtypes = [P(_TT), P(_TT), C.c_int32, P(sz)]
     L.qtt_dot.argtypes = [P(_TT), P(_TT), P(C.c_double), vp, sz, vp]
     L.qtt_axpby.argtypes = [C.c_double, P(_TT), C.c_double, P(_TT), P(_TT), vp, sz, vp]
     L.qtt_assemble_stiffness.argtypes = [P(_Problem), C.c_double, P(_TT), P(_TT), vp, sz, vp]
@@ -93,7 +97,7 @@ def load_library(path: str = LIB_PATH):
                             vp, sz, vp]
     L.qtt_solve_workspace.argtypes = [P(_TT), P(_TT), P(_SolveOpts), P(sz)]
     for name in ("qtt_matvec", "qtt_round", "qtt_round_workspace", "qtt_round_sketch",
-                 "qtt_round_sketch_workspace",
+                 "qtt_round_sketch_workspace", "qtt_matvec_round", "qtt_matvec_round_workspace",
                  "qtt_dot", "qtt_axpby",
                  "qtt_assemble_stiffness", "qtt_assemble_workspace", "qtt_assemble_bpx", "qtt_solve",
                  "qtt_solve_workspace"):
@@ -246,6 +250,30 @@ def round_sketch(x: TT, ell: int, seed: int, eps: float, rmax: int = 0):
                                   C.byref(nrm), C.byref(err), C.c_void_p(_aligned_ptr(ws)),
                                   ws.numel() - 256, _stream_ptr()))
     return nrm.value, err.value
+
+
+def matvec_round_workspace(A: TT, x: TT, ell: int):
+    need = C.c_size_t()
+    _check(lib().qtt_matvec_round_workspace(C.byref(A.c), C.byref(x.c), int(ell), C.byref(need)))
+    return _workspace(need.value)
+
+
+def matvec_round(A: TT, x: TT, ell: int, seed: int, eps: float, rmax: int, compute: str = "f64",
+                 y: Optional[TT] = None, ws=None):
+    """y = round(A x): product, sketch of rank ell (0: none) and exact
+    rounding in one call; returns (y, norm, discarded bound)."""
+    D = A.D
+    if y is None:
+        r = max(rmax, 1) if rmax > 0 else max(a * b for a, b in zip(A.ranks, x.ranks))
+        y = TT(A.nrow, None, [1] * (D + 1), sum(r * r * A.nrow[k] for k in range(D)))
+    if ws is None:
+        ws = matvec_round_workspace(A, x, ell)
+    nrm, err = C.c_double(), C.c_double()
+    _check(lib().qtt_matvec_round(C.byref(A.c), C.byref(x.c), C.byref(y.c), _DTYPES[compute],
+                                  int(ell), int(seed), float(eps), int(rmax), C.byref(nrm),
+                                  C.byref(err), C.c_void_p(_aligned_ptr(ws)), ws.numel() - 256,
+                                  _stream_ptr()))
+    return y, nrm.value, err.value
 
 
 def dot(x: TT, y: TT) -> float:

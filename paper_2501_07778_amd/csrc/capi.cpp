@@ -283,6 +283,110 @@ qtt_status qtt_round_sketch(qtt_tt *x, int32_t ell, uint64_t seed, double eps, i
   return QTT_OK;
 }
 
+// ---------------------------------------------------------------- fused step
+static qtt_status check_matvec_args(const qtt_tt *A, const qtt_tt *x, qtt_dtype compute) {
+  qtt_status st;
+  if ((st = check_tt(A, "A", true)) != QTT_OK) return st;
+  if ((st = check_tt(x, "x", true)) != QTT_OK) return st;
+  if (!A->ncol) return fail(QTT_E_INVAL, "A must be a matrix (ncol != NULL)");
+  if (x->ncol) return fail(QTT_E_INVAL, "x must be a vector");
+  if (A->ncores != x->ncores) return fail(QTT_E_SHAPE, "core counts differ");
+  for (int k = 0; k < A->ncores; ++k) {
+    if (A->ncol[k] != x->nrow[k]) return fail(QTT_E_SHAPE, "A column mode != x mode");
+    if (A->ncol[k] > 8) return fail(QTT_E_UNSUPPORTED, "column mode > 8");
+  }
+  if (compute != QTT_F64 && compute != QTT_F32 && compute != QTT_BF16)
+    return fail(QTT_E_INVAL, "bad compute dtype");
+  return QTT_OK;
+}
+
+// carve the product train (caps = product ranks) and the rounding and
+// sketch workspaces
+static bool carve_matvec_round(Arena &ar, const qtt_tt *A, const qtt_tt *x, int32_t ell,
+                               TTDesc &t, RoundWs &w, double *&sk, int32_t *&rk) {
+  const int D = A->ncores;
+  std::vector<int> caps(D + 1);
+  for (int k = 0; k <= D; ++k) caps[k] = A->ranks[k] * x->ranks[k];
+  arena_tt(ar, t, D, A->nrow, nullptr, caps);
+  round_ws_take(ar, t.v, w);
+  sk = ell > 0 ? (double *)ar.take(sizeof(double) * sketch_ws_elems(t.v, ell)) : nullptr;
+  rk = (int32_t *)ar.take(sizeof(int32_t) * 2 * (QTT_MAXD + 1));
+  return ar.ok();
+}
+
+qtt_status qtt_matvec_round_workspace(const qtt_tt *A, const qtt_tt *x, int32_t ell,
+                                      size_t *bytes) {
+  qtt_status st;
+  if ((st = check_matvec_args(A, x, QTT_F64)) != QTT_OK) return st;
+  if (ell < 0 || ell > 512) return fail(QTT_E_INVAL, "ell must be in 0..512");
+  if (!bytes) return fail(QTT_E_INVAL, "bytes is NULL");
+  Arena ar;
+  ar.dry = true;
+  TTDesc t;
+  RoundWs w;
+  double *sk;
+  int32_t *rk;
+  carve_matvec_round(ar, A, x, ell, t, w, sk, rk);
+  *bytes = ar.used + 256;
+  return QTT_OK;
+}
+
+qtt_status qtt_matvec_round(const qtt_tt *A, const qtt_tt *x, qtt_tt *y, qtt_dtype compute,
+                            int32_t ell, uint64_t seed, double eps, int32_t rmax, double *norm,
+                            double *err, void *ws, size_t ws_bytes, void *stream) {
+  qtt_status st;
+  if ((st = check_matvec_args(A, x, compute)) != QTT_OK) return st;
+  if (!y || !y->ranks || !y->nrow || !y->data) return fail(QTT_E_INVAL, "y: NULL field");
+  if (y->ncores != A->ncores || y->ncol) return fail(QTT_E_SHAPE, "y must be a vector like x");
+  for (int k = 0; k < A->ncores; ++k)
+    if (y->nrow[k] != A->nrow[k]) return fail(QTT_E_SHAPE, "y mode != A row mode");
+  if (ell < 0 || ell > 512) return fail(QTT_E_INVAL, "ell must be in 0..512");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(QTT_E_INVAL, "eps must be >= 0");
+  if (!ws) return fail(QTT_E_CAPACITY, "workspace is NULL");
+  Arena ar;
+  ar.base = (char *)ws;
+  ar.size = ws_bytes;
+  TTDesc t;
+  RoundWs w;
+  double *sk;
+  int32_t *rk;
+  if (!carve_matvec_round(ar, A, x, ell, t, w, sk, rk))
+    return fail(QTT_E_CAPACITY, "workspace too small for qtt_matvec_round: need " +
+                                    std::to_string(ar.used));
+  const int D = A->ncores;
+  hipStream_t s = (hipStream_t)stream;
+  TTView va, vx;
+  packed_view(A, va, rk);
+  packed_view(x, vx, rk + (QTT_MAXD + 1));
+  QTT_HIP(upload_ranks(va, A->ranks, s));
+  QTT_HIP(upload_ranks(vx, x->ranks, s));
+  // the product goes straight into the slotted train (the kernel writes its
+  // device ranks), then sketch and rounding work on it in place
+  QTT_HIP(launch_matvec(va, vx, t.v, compute, s));
+  if (ell > 0) {
+    QTT_HIP(sketch_tt(t.v, ell, seed, 0, sk, s));
+    QTT_HIP(round_tt(t.v, eps, rmax, w, s, true, ell));
+  } else {
+    QTT_HIP(round_tt(t.v, eps, rmax, w, s));
+  }
+  int32_t rk_host[QTT_MAXD + 1];
+  double scal[2];
+  QTT_HIP(hipMemcpyAsync(rk_host, t.v.rk, sizeof(int32_t) * (D + 1), hipMemcpyDeviceToHost, s));
+  QTT_HIP(hipMemcpyAsync(scal, w.scal, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+  QTT_HIP(hipStreamSynchronize(s));
+  int64_t need = 0;
+  for (int k = 0; k < D; ++k) need += (int64_t)rk_host[k] * y->nrow[k] * rk_host[k + 1];
+  if (need > y->capacity)
+    return fail(QTT_E_CAPACITY, "y: capacity " + std::to_string(y->capacity) + " < " +
+                                    std::to_string(need));
+  QTT_HIP(launch_pack(t.v, (double *)y->data, s));
+  QTT_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k <= D; ++k) y->ranks[k] = rk_host[k];
+  if (norm) *norm = scal[0];
+  if (err) *err = std::sqrt(scal[1] > 0.0 ? scal[1] : 0.0);
+  return QTT_OK;
+}
+
 qtt_status qtt_dot(const qtt_tt *x, const qtt_tt *y, double *out, void *ws,
                    size_t ws_bytes, void *stream) {
   qtt_status st;

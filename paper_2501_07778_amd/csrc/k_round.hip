@@ -24,7 +24,7 @@ namespace {
 constexpr int WG = 1024;           // threads of the one-workgroup kernels
 constexpr int NWAVE = WG / 64;
 constexpr int JACOBI_MAX_SWEEPS = 40;
-constexpr int GL = 32;             // lanes per column pair in the Jacobi sweeps
+constexpr int GL = 16;             // lanes per column pair in the Jacobi sweeps
 constexpr int NGRP = WG / GL;
 // LDS-resident variants hold the whole working set of one step (matrix and
 // its second factor) in 150 KiB of LDS
@@ -288,7 +288,7 @@ __device__ __forceinline__ double group_sum(double v) {
 
 // One-sided Jacobi (Hestenes) on the columns of B (mb x nb, ld = mb) with V
 // (nb x nb) accumulated: B V has mutually orthogonal columns.  Round-robin
-// ordering: each round pairs all columns disjointly, one 32-lane group per
+// ordering: each round pairs all columns disjointly, one 16-lane group per
 // pair.  A pair is rotated while |b_p . b_q| > tol ||b_p|| ||b_q||; since V
 // stays orthogonal, B_in = (B V) V^T holds whatever tol is, and columns
 // dropped later contribute exactly their norms to the truncation error.

@@ -175,3 +175,27 @@ def test_sketch_rounding_against_exact(P, ell, eps):
     opt, _ = T.tt_round(y, 0.0, ell, return_info=True)
     best = np.linalg.norm(T.full_vector(opt) - yd)
     assert np.linalg.norm(gd - yd) <= 10 * best + 2 * eps * np.linalg.norm(yd)
+
+
+@pytest.mark.parametrize("ell", [0, 40])
+def test_matvec_round_fused(P, ell):
+    """qtt_matvec_round equals round(A x) of the oracle (exact path) and the
+    separate product + sketch rounding (same seed, same sketch)."""
+    from oracle import assembly as A
+    Kq, fq = A.assemble_qtt(W.cantilever_traction(5))
+    x = T.tt_round(_vec(3, [2] * 11, 6), 0.0)
+    yref = T.full_vector(T.matvec(Kq, x))
+    K, tx = P.tt_from_cores(Kq), P.tt_from_cores(x)
+    y, nrm, err = P.matvec_round(K, tx, ell, 9, 1e-10, 0)
+    yd = T.full_vector(P.tt_to_cores(y))
+    assert nrm == pytest.approx(np.linalg.norm(yref), rel=1e-10)
+    if ell == 0:
+        ref = T.full_vector(T.tt_round(T.matvec(Kq, x), 1e-10))
+        assert np.linalg.norm(yd - ref) <= 1e-12 * np.linalg.norm(yref) + 2e-10 * np.linalg.norm(yref)
+        assert np.linalg.norm(yd - yref) <= 1e-10 * np.linalg.norm(yref) * (1 + 1e-6)
+    else:
+        t = P.matvec(K, tx)
+        P.round_sketch(t, ell, 9, 1e-10, 0)
+        td = T.full_vector(P.tt_to_cores(t))
+        assert y.ranks == t.ranks
+        assert np.linalg.norm(yd - td) <= 1e-12 * np.linalg.norm(yref)
