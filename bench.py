@@ -42,6 +42,8 @@ def _parse():
     ap.add_argument("--level", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--batch", type=int, default=64,
+                    help="cases of the batched-step measurement (0: skip)")
     return ap.parse_args()
 
 
@@ -86,6 +88,72 @@ def matvec_roofline(P, torch, K, x):
     return dict(kernel="k_matvec_f64", bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,
                 bytes_per_launch=nbytes, ms_per_launch=round(ms, 4))
+
+
+def rel_diff(P, a, b) -> float:
+    """||a - b|| / ||b|| from three inner products of the (rank <= 64)
+    trains, FP64 on the device."""
+    aa, bb, ab = P.dot(a, a), P.dot(b, b), P.dot(a, b)
+    return (max(aa + bb - 2.0 * ab, 0.0) ** 0.5) / bb ** 0.5
+
+
+def mixed_precision(P, torch, K, x, ws, steps):
+    """The same step with the product in FP32 and BF16 (FP32 accumulation;
+    sketch GEMMs, QR and SVD stay FP64), same sketch seed: time per step and
+    relative error of the result against the FP64 step."""
+    y64 = step(P, K, x, None, ws, 0, "f64")
+    out = {}
+    for comp in ("f32", "bf16"):
+        y = step(P, K, x, None, ws, 0, comp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            y = step(P, K, x, y, ws, 0, comp)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[comp] = dict(ms_per_step=round(1e3 * dt, 3),
+                         rel_err_vs_f64_gpu=float("%.3e" % rel_diff(P, y, y64)))
+    return out
+
+
+def batched_steps(P, torch, ncases: int):
+    """The hot step on the batched configuration's shapes: case i draws its
+    level (8..11) and rank cap (16..96) from rng(1000 + i); K of that level,
+    x a seeded train at the cap, y = round(K x) to (1e-6, cap) via a sketch
+    of rank cap + 8.  Cases run concurrently by host workers on their own
+    streams (qtt_matvec_round_batched); the worker count is tuned here."""
+    import workloads as W
+    Ks = {}
+    items = []
+    nbytes = 0
+    for i in range(ncases):
+        c = W.batch_case(i)
+        lvl, cap = c.level, c.cap
+        if lvl not in Ks:
+            Ks[lvl], _ = P.assemble(W.cantilever_traction(lvl))
+        K = Ks[lvl]
+        modes = [2] * (2 * lvl + 1)
+        x = P.tt_from_cores(W.random_tt_cores(7000 + i, modes, W.capped_ranks(modes, cap)))
+        items.append((K, x, cap + 8, i, 1e-6, cap, "f64"))
+        prod = 8 * sum(K.ranks[k] * x.ranks[k] * 2 * K.ranks[k + 1] * x.ranks[k + 1]
+                       for k in range(K.D))
+        nbytes += tt_bytes(K) + tt_bytes(x) + 2 * prod
+    rates = {}
+    batch = P.StepBatch(items, 1)
+    for nw in (1, 4, 8, 16, 32):
+        batch.set_workers(nw)
+        P.matvec_round_batched(batch)          # warm-up of this worker set
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.matvec_round_batched(batch)
+        torch.cuda.synchronize()
+        rates[nw] = time.perf_counter() - t0
+    best = min(rates, key=rates.get)
+    levels = sorted(set(W.batch_case(i).level for i in range(ncases)))
+    return dict(cases=ncases, levels=levels, best_workers=best,
+                steps_per_s={str(k): round(ncases / v, 2) for k, v in rates.items()},
+                gbs_at_best=round(nbytes / rates[best] / 1e9, 2),
+                speedup_vs_1_worker=round(rates[1] / rates[best], 2))
 
 
 def cpu_baseline(level, nbytes, seconds):
@@ -140,6 +208,9 @@ def main():
         print("bench.py runs on one GPU only: the multi-GPU form (independent load cases "
               "per GPU) is not built", file=sys.stderr)
         sys.exit(2)
+    # concurrent streams of the batched measurement: one hardware queue each
+    # (HIP's default is 4 per process)
+    os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
     import torch
     import paper_2501_07778_amd as P
 
@@ -160,6 +231,8 @@ def main():
     nbytes = tt_bytes(K) + tt_bytes(x) + 2 * prod + tt_bytes(y)
     value = nbytes / dt / 1e9
     roof = matvec_roofline(P, torch, K, x)
+    mixed = mixed_precision(P, torch, K, x, ws, max(2, args.steps // 2))
+    batched = batched_steps(P, torch, args.batch) if args.batch > 0 else None
     line = {
         "metric": "QTT solves/sec and matvec+round GB/s at rel. err 1e-6 vs FP64 plain GPU",
         "value": round(value, 3),
@@ -178,7 +251,8 @@ def main():
                                "round to eps %.0e / rank %d via sketch %d"
                                % (args.level, 2 * 4 ** args.level, K.D, max(K.ranks), RANK,
                                   EPS, RANK, ELL),
-                   "bytes_per_step": nbytes, "result_ranks_max": max(y.ranks)},
+                   "bytes_per_step": nbytes, "result_ranks_max": max(y.ranks),
+                   "mixed_precision": mixed, "batched_steps": batched},
         "roofline": roof,
     }
     if not args.no_cpu:

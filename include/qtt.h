@@ -222,8 +222,10 @@ typedef struct {
                         CHEBYSHEV, FCG: iterations in total                   */
   int32_t maxit_out; /* CG_IR: refinement steps                              */
   int32_t check_every; /* iterations between host convergence checks        */
-  qtt_dtype compute; /* contractions: QTT_F64, QTT_F32 or QTT_BF16 (QR, SVD,
-                        dot products and the outer residual stay FP64)       */
+  qtt_dtype compute; /* products of the correction: QTT_F64, QTT_F32 or
+                        QTT_BF16 with FP32 accumulation (CG_IR: K p; CHEBYSHEV
+                        and FCG: C r and the power steps); the residual
+                        f - K u, QR, SVD and inner products stay FP64        */
   int32_t sketch;    /* 0: exact rounding of every product; > 0: round
                         products by a randomised sketch of this oversampling
                         before the exact rounding                            */
@@ -277,6 +279,64 @@ qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
                      void *stream);
 qtt_status qtt_solve_workspace(const qtt_tt *K, const qtt_tt *f,
                                const qtt_solve_opts *opts, size_t *bytes);
+
+/* ------------------------------------------------------------ batched  */
+/* One independent solve of a batch: the arguments of qtt_solve, with its
+ * own workspace and stream (streams of default priority, all on one
+ * device).                                                                 */
+typedef struct {
+  const qtt_tt *K, *f, *x0;
+  const qtt_solve_opts *opts;
+  qtt_tt *u;
+  qtt_solve_report *report;
+  void *ws;
+  size_t ws_bytes;
+  void *stream;
+  int32_t status;         /* written: the case's qtt_status                 */
+} qtt_solve_case;
+
+/* qtt_solve_batched — many load cases (any levels, ranks and options) solved
+ * concurrently: `concurrency` host workers each take the next unsolved case
+ * and run qtt_solve on that case's stream, so up to `concurrency` solves
+ * keep the GPU busy at once (each solve alone is a chain of small,
+ * mostly one-workgroup kernels).  concurrency <= 0 uses the value the
+ * autotuner stored for the batch's largest level, else 8.  Returns QTT_OK
+ * when every case converged, otherwise the first failing case's status;
+ * every case's own status is in cases[i].status.  Synchronises all the
+ * cases' streams.  No multi-GPU split: the batch runs on the current
+ * device.                                                                  */
+qtt_status qtt_solve_batched(int32_t n, qtt_solve_case *cases, int32_t concurrency);
+
+/* qtt_autotune_batched — times qtt_solve_batched on the given cases at
+ * concurrency 1, 2, 4, 8, 16 and 32 (each run solves all n cases), stores
+ * the fastest for the batch's largest level and returns it in *best (and
+ * the solves/s of each candidate in rates[6] when rates is not NULL).  The
+ * cases' results are those of the last run.                                */
+qtt_status qtt_autotune_batched(int32_t n, qtt_solve_case *cases, int32_t *best,
+                                double *rates);
+
+/* One y = round(A x) of a batch of hot steps (arguments of qtt_matvec_round
+ * without the workspace and stream, which belong to the workers).          */
+typedef struct {
+  const qtt_tt *A, *x;
+  qtt_tt *y;
+  qtt_dtype compute;
+  int32_t ell;
+  uint64_t seed;
+  double eps;
+  int32_t rmax;
+  double norm, err;       /* written */
+  int32_t status;         /* written */
+} qtt_matvec_round_case;
+
+/* qtt_matvec_round_batched — n independent hot steps (any levels and ranks)
+ * run by `nworkers` host workers, worker w using ws[w] (ws_bytes[w] bytes,
+ * enough for the largest case: qtt_matvec_round_workspace) and streams[w].
+ * Returns QTT_OK or the first failing case's status (each case's own in
+ * cases[i].status).  Synchronises the workers' streams.                    */
+qtt_status qtt_matvec_round_batched(int32_t n, qtt_matvec_round_case *cases, int32_t nworkers,
+                                    void *const *ws, const size_t *ws_bytes,
+                                    void *const *streams);
 
 /* Thread-local text of the last error of this thread.                      */
 const char *qtt_last_error(void);

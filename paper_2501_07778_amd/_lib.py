@@ -61,6 +61,20 @@ class _SolveReport(C.Structure):
                 ("max_rank", C.c_int32), ("criterion", C.c_double), ("lmax", C.c_double)]
 
 
+class _SolveCase(C.Structure):
+    _fields_ = [("K", C.POINTER(_TT)), ("f", C.POINTER(_TT)), ("x0", C.POINTER(_TT)),
+                ("opts", C.POINTER(_SolveOpts)), ("u", C.POINTER(_TT)),
+                ("report", C.POINTER(_SolveReport)), ("ws", C.c_void_p),
+                ("ws_bytes", C.c_size_t), ("stream", C.c_void_p), ("status", C.c_int32)]
+
+
+class _MVRCase(C.Structure):
+    _fields_ = [("A", C.POINTER(_TT)), ("x", C.POINTER(_TT)), ("y", C.POINTER(_TT)),
+                ("compute", C.c_int32), ("ell", C.c_int32), ("seed", C.c_uint64),
+                ("eps", C.c_double), ("rmax", C.c_int32), ("norm", C.c_double),
+                ("err", C.c_double), ("status", C.c_int32)]
+
+
 _lib = None
 
 
@@ -96,11 +110,16 @@ def load_library(path: str = LIB_PATH):
     L.qtt_solve.argtypes = [P(_TT), P(_TT), P(_TT), P(_SolveOpts), P(_TT), P(_SolveReport),
                             vp, sz, vp]
     L.qtt_solve_workspace.argtypes = [P(_TT), P(_TT), P(_SolveOpts), P(sz)]
+    L.qtt_solve_batched.argtypes = [C.c_int32, P(_SolveCase), C.c_int32]
+    L.qtt_matvec_round_batched.argtypes = [C.c_int32, P(_MVRCase), C.c_int32, P(vp), P(sz),
+                                           P(vp)]
+    L.qtt_autotune_batched.argtypes = [C.c_int32, P(_SolveCase), P(C.c_int32), P(C.c_double)]
     for name in ("qtt_matvec", "qtt_round", "qtt_round_workspace", "qtt_round_sketch",
                  "qtt_round_sketch_workspace", "qtt_matvec_round", "qtt_matvec_round_workspace",
                  "qtt_dot", "qtt_axpby",
                  "qtt_assemble_stiffness", "qtt_assemble_workspace", "qtt_assemble_bpx", "qtt_solve",
-                 "qtt_solve_workspace"):
+                 "qtt_solve_workspace", "qtt_solve_batched", "qtt_autotune_batched",
+                 "qtt_matvec_round_batched"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -415,3 +434,118 @@ def solve(K: TT, f: TT, opts: SolveOpts, x0: Optional[TT] = None, ws=None):
                   residual_hist=[rep.residual_hist[i] for i in range(min(nh, 64))],
                   max_rank=rep.max_rank, criterion=rep.criterion, lmax=rep.lmax)
     return u, report
+
+
+def _report_dict(rep, opts):
+    nh = rep.outer + 1 if opts.method == "cg" else rep.inner // max(opts.check_every, 1) + 1
+    return dict(status=rep.status, outer=rep.outer, inner=rep.inner, residual=rep.residual,
+                residual_hist=[rep.residual_hist[i] for i in range(min(nh, 64))],
+                max_rank=rep.max_rank, criterion=rep.criterion, lmax=rep.lmax)
+
+
+class Batch:
+    """Buffers of a batch of independent solves: per case the solution
+    train, a report, a workspace and a stream (default priority)."""
+
+    def __init__(self, problems):
+        torch = _torch()
+        self.items = []
+        for (K, f, opts) in problems:
+            D = K.D
+            u_cap = sum(opts.rmax ** 2 * K.nrow[k] for k in range(D))
+            u = TT(K.nrow, None, [1] * (D + 1), u_cap)
+            o = opts.c()
+            ws = _workspace(solve_workspace_bytes(K, f, opts))
+            st = torch.cuda.Stream()
+            self.items.append(dict(K=K, f=f, opts=opts, o=o, u=u, rep=_SolveReport(), ws=ws,
+                                   stream=st))
+        n = len(self.items)
+        self.cases = (_SolveCase * max(n, 1))()
+        for i, it in enumerate(self.items):
+            c = self.cases[i]
+            c.K = C.pointer(it["K"].c)
+            c.f = C.pointer(it["f"].c)
+            c.x0 = None
+            c.opts = C.pointer(it["o"])
+            c.u = C.pointer(it["u"].c)
+            c.report = C.pointer(it["rep"])
+            c.ws = _aligned_ptr(it["ws"])
+            c.ws_bytes = it["ws"].numel() - 256
+            c.stream = it["stream"].cuda_stream
+        self.n = n
+
+    def results(self):
+        return [(it["u"], _report_dict(it["rep"], it["opts"])) for it in self.items]
+
+
+def solve_batched(batch: Batch, concurrency: int = 0):
+    """qtt_solve_batched over the batch; returns [(u, report)] and raises on
+    a failing case other than non-convergence."""
+    _torch().cuda.synchronize()
+    st = lib().qtt_solve_batched(batch.n, batch.cases, int(concurrency))
+    if st not in (0, -4):
+        _check(st)
+    return batch.results()
+
+
+def autotune_batched(batch: Batch):
+    """qtt_autotune_batched: the best concurrency and the solves/s of the
+    candidates 1, 2, 4, 8, 16, 32."""
+    _torch().cuda.synchronize()
+    best = C.c_int32()
+    rates = (C.c_double * 6)()
+    _check(lib().qtt_autotune_batched(batch.n, batch.cases, C.byref(best), rates))
+    return best.value, dict(zip([1, 2, 4, 8, 16, 32], list(rates)))
+
+
+class StepBatch:
+    """A batch of hot steps y_i = round(A_i x_i) (qtt_matvec_round_batched):
+    the outputs, and one workspace and stream per worker sized for the
+    largest case."""
+
+    def __init__(self, items, nworkers: int):
+        torch = _torch()
+        self.items = []
+        need = 0
+        for (A, x, ell, seed, eps, rmax, compute) in items:
+            D = A.D
+            r = rmax if rmax > 0 else max(a * b for a, b in zip(A.ranks, x.ranks))
+            y = TT(A.nrow, None, [1] * (D + 1), sum(r * r * A.nrow[k] for k in range(D)))
+            n = C.c_size_t()
+            _check(lib().qtt_matvec_round_workspace(C.byref(A.c), C.byref(x.c), int(ell),
+                                                    C.byref(n)))
+            need = max(need, n.value)
+            self.items.append((A, x, y, ell, seed, eps, rmax, compute))
+        self.n = len(self.items)
+        self.cases = (_MVRCase * max(self.n, 1))()
+        for i, (A, x, y, ell, seed, eps, rmax, compute) in enumerate(self.items):
+            c = self.cases[i]
+            c.A, c.x, c.y = C.pointer(A.c), C.pointer(x.c), C.pointer(y.c)
+            c.compute, c.ell, c.seed, c.eps, c.rmax = _DTYPES[compute], ell, seed, eps, rmax
+        self.set_workers(nworkers, need)
+
+    def set_workers(self, nworkers: int, need: int = None):
+        """Use `nworkers` workers; workspaces and streams are kept in a pool
+        and reused when the count changes."""
+        torch = _torch()
+        if need is not None:
+            self.need = need
+            self._ws, self._st = [], []
+        while len(self._ws) < nworkers:
+            self._ws.append(_workspace(self.need))
+            self._st.append(torch.cuda.Stream())
+        self.nworkers = nworkers
+        ws, st = self._ws[:nworkers], self._st[:nworkers]
+        self.ws_ptr = (C.c_void_p * nworkers)(*[_aligned_ptr(w) for w in ws])
+        self.ws_len = (C.c_size_t * nworkers)(*[w.numel() - 256 for w in ws])
+        self.st_ptr = (C.c_void_p * nworkers)(*[x.cuda_stream for x in st])
+
+    def outputs(self):
+        return [it[2] for it in self.items]
+
+
+def matvec_round_batched(batch: StepBatch):
+    _torch().cuda.synchronize()
+    _check(lib().qtt_matvec_round_batched(batch.n, batch.cases, batch.nworkers, batch.ws_ptr,
+                                          batch.ws_len, batch.st_ptr))
+    return batch.outputs()

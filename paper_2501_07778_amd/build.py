@@ -26,6 +26,7 @@ SOURCES = [
     "k_round.hip",
     "k_sketch.hip",
     "k_full.hip",
+    "batched.cpp",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -383,10 +383,12 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
     bool have_d = false;
     int it = 0;
     for (it = 0; it <= o->maxit_in; ++it) {
-      // r = round(f - K u): exact product and difference, then rounding
-      // relative to ||r||
+      // r = round(f - K u): exact FP64 product and difference, then rounding
+      // relative to ||r|| (the residual sets the attainable accuracy, so it
+      // stays FP64 in every compute mode; the low-precision mode applies to
+      // the preconditioner product C r only)
       if (have_u) {
-        QTT_HIP(launch_matvec(Kv, L.U[cur].v, L.Ku.v, lowp, s));
+        QTT_HIP(launch_matvec(Kv, L.U[cur].v, L.Ku.v, QTT_F64, s));
         QTT_HIP(launch_axpby(1.0, nullptr, fv, -1.0, nullptr, L.Ku.v, L.R.v, s));
       } else {
         QTT_HIP(launch_copy_tt(fv, L.R.v, s));

@@ -199,3 +199,23 @@ def test_matvec_round_fused(P, ell):
         td = T.full_vector(P.tt_to_cores(t))
         assert y.ranks == t.ranks
         assert np.linalg.norm(yd - td) <= 1e-12 * np.linalg.norm(yref)
+
+
+def test_matvec_round_batched_equals_single(P):
+    """Hot steps of different levels and ranks run by 3 workers on their own
+    streams equal the same steps run one at a time (same sketch seeds)."""
+    from oracle import assembly as A
+    items = []
+    for i, (d, r) in enumerate([(4, 8), (5, 12), (3, 5), (6, 16), (5, 7)]):
+        Kq, _ = A.assemble_qtt(W.cantilever_traction(d))
+        modes = [2] * (2 * d + 1)
+        x = W.random_tt_cores(20 + i, modes, W.capped_ranks(modes, r))
+        items.append((P.tt_from_cores(Kq), P.tt_from_cores(x), 24 if i % 2 else 0, 7 + i,
+                      1e-8, 20, "f64"))
+    batch = P.StepBatch(items, 3)
+    outs = P.matvec_round_batched(batch)
+    for (K, x, ell, seed, eps, rmax, comp), y in zip(items, outs):
+        y1, _, _ = P.matvec_round(K, x, ell, seed, eps, rmax, comp)
+        assert y.ranks == y1.ranks
+        a, b = T.full_vector(P.tt_to_cores(y)), T.full_vector(P.tt_to_cores(y1))
+        assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b)

@@ -210,3 +210,54 @@ def test_bpx_solves_reject_bad_options(P):
         P.solve(K, f, P.SolveOpts(method="chebyshev", precond=C, rmax=16, rmax_in=32))
     with pytest.raises(P.QttError):
         P.solve(K, f, P.SolveOpts(method="fcg"))                 # no preconditioner
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_mixed_precision_fcg(P, compute):
+    """Products of the correction (C r) in FP32 or BF16 with FP32
+    accumulation, residual and rounding in FP64: the solve still reaches the
+    FP64 solution; error reported against the oracle's direct solve and
+    against the FP64 GPU solve."""
+    d = 5
+    prob = W.cantilever_traction(d)
+    uref, _ = fem.solve_problem(prob)
+    K, f = P.assemble(prob)
+    C = P.assemble_bpx(prob)
+    base = dict(tol=1e-9, eps=1e-11, rmax=64, eps_in=1e-3, rmax_in=32, maxit_in=600,
+                check_every=5, precond=C, method="fcg")
+    u64, rep64 = P.solve(K, f, P.SolveOpts(**base))
+    ulp, replp = P.solve(K, f, P.SolveOpts(compute=compute, **base))
+    d64 = T.full_vector(P.tt_to_cores(u64))
+    dlp = T.full_vector(P.tt_to_cores(ulp))
+    assert rep64["status"] == 0 and replp["status"] == 0
+    err_oracle = np.linalg.norm(dlp - uref) / np.linalg.norm(uref)
+    err_gpu64 = np.linalg.norm(dlp - d64) / np.linalg.norm(d64)
+    print("mixed %s: iterations %d (FP64 %d), error vs oracle %.2e, vs FP64 GPU %.2e"
+          % (compute, replp["inner"], rep64["inner"], err_oracle, err_gpu64))
+    assert err_oracle <= 1e-8 and err_gpu64 <= 1e-8
+
+
+def test_batched_solves_equal_single_solves(P):
+    """Load cases of different levels, seeds and inner rank caps solved
+    concurrently (qtt_solve_batched, 4 workers on their own streams) give the
+    same iterates as one solve at a time; the autotuner returns one of its
+    candidates and a rate for each."""
+    cases = []
+    for i, d in enumerate([3, 4, 3, 5, 4, 3]):
+        prob = W.cantilever_traction(d, seed=i)
+        K, f = P.assemble(prob)
+        C = P.assemble_bpx(prob)
+        opts = P.SolveOpts(tol=1e-9, eps=1e-11, rmax=64, eps_in=1e-3, rmax_in=16 + 8 * (i % 3),
+                           maxit_in=400, check_every=5, precond=C, method="fcg")
+        cases.append((K, f, opts))
+    batch = P.Batch(cases)
+    res = P.solve_batched(batch, 4)
+    for (K, f, opts), (u, rep) in zip(cases, res):
+        u1, rep1 = P.solve(K, f, opts)
+        assert rep["status"] == 0 and rep["inner"] == rep1["inner"]
+        assert u.ranks == u1.ranks
+        a, b = T.full_vector(P.tt_to_cores(u)), T.full_vector(P.tt_to_cores(u1))
+        assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b)
+    small = P.Batch(cases[:3:2])                      # two level-3 cases
+    best, rates = P.autotune_batched(small)
+    assert best in rates and all(r > 0 for r in rates.values())
