@@ -30,6 +30,8 @@ constexpr int NGRP = WG / GL;
 // its second factor) in 150 KiB of LDS
 constexpr int LDS_DBL = 19200;
 constexpr int LDS_TAU = 160;       // min(rows, cols) <= sqrt(LDS_DBL)
+// the SVD step keeps nothing else in LDS, so its array can take 159 KiB
+constexpr int LDS_SVD = 20352;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -150,6 +152,28 @@ __device__ void form_q(const double *W, int rows, int kq, const double *tau,
         s = wave_sum(s) * t;
         if (lane == 0) qc[j] -= s;
         for (int i = j + 1 + lane; i < rows; i += 64) qc[i] -= s * wj[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Y (rows x ncols, ld = rows) <- H_0 H_1 ... H_{kq-1} Y with the reflectors
+// stored below the diagonal of W (householder_qr layout)
+__device__ void apply_q(const double *W, int rows, int kq, const double *tau, double *Y,
+                        int ncols) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = kq - 1; j >= 0; --j) {
+    const double t = tau[j];
+    if (t != 0.0) {
+      const double *wj = W + (int64_t)rows * j;
+      for (int c = wave; c < ncols; c += NWAVE) {
+        double *yc = Y + (int64_t)rows * c;
+        double s = (lane == 0) ? yc[j] : 0.0;
+        for (int i = j + 1 + lane; i < rows; i += 64) s += wj[i] * yc[i];
+        s = wave_sum(s) * t;
+        if (lane == 0) yc[j] -= s;
+        for (int i = j + 1 + lane; i < rows; i += 64) yc[i] -= s * wj[i];
       }
     }
     __syncthreads();
@@ -483,7 +507,7 @@ __global__ void __launch_bounds__(WG)
                int *iwork, double *scal, double *rot_log) {
   __shared__ int flag;
   __shared__ int rank_s;
-  __shared__ double lds[LDS ? LDS_DBL : 1];
+  __shared__ double lds[LDS ? LDS_SVD : 1];
   IW w = iw_of(iwork, x.D);
   const int D = x.D;
   const int nm = x.n[k] * x.m[k];
@@ -492,6 +516,51 @@ __global__ void __launch_bounds__(WG)
   const bool tall = r0 >= nc;
   const int mb = tall ? r0 : nc, nb = tall ? nc : r0;
   if (r0 > x.cap[k] || w.fr[k + 1] > x.cap[k + 1]) return;  // ranks beyond the slots
+  const double delta0 = (D > 1) ? eps * scal[0] / sqrt((double)(D - 1)) : 0.0;
+  double *core0 = x.data + x.off[k];
+  if (LDS && !tall && (int64_t)mb * nb + 2 * (int64_t)nb * nb <= LDS_SVD) {
+    // Wide unfolding M (r0 x nc): QR of B = M^T = Q R, one-sided Jacobi on
+    // X = R^T (r0 x r0) with X V = W, so M = W (Q V)^T.  The kept core rows
+    // (Q V)^T are orthonormal for any Jacobi tolerance (V is a product of
+    // rotations), which allows the same loose tolerance as the tall case,
+    // and the Jacobi works on r0-long instead of nc-long columns.
+    double *Bq = lds;                        // nc x r0, then R and reflectors
+    double *X = lds + (int64_t)mb * nb;      // r0 x r0
+    double *Vv = X + (int64_t)nb * nb;       // r0 x r0
+    __shared__ double red[NWAVE];
+    for (int64_t e = threadIdx.x; e < (int64_t)mb * nb; e += WG) {
+      const int i = (int)(e % mb), j = (int)(e / mb);
+      Bq[e] = carry[j + (int64_t)r0 * i];
+    }
+    __syncthreads();
+    double *tau = vbuf;
+    householder_qr(Bq, mb, nb, tau, red);
+    for (int64_t e = threadIdx.x; e < (int64_t)nb * nb; e += WG) {
+      const int i = (int)(e % nb), j = (int)(e / nb);
+      X[e] = (j <= i) ? Bq[j + (int64_t)mb * i] : 0.0;  // X[i, j] = R[j, i]
+    }
+    __syncthreads();
+    jacobi(X, nb, nb, Vv, nullptr, &flag, jacobi_tol(eps, nb));
+    const int rank = truncate_rank(X, nb, nb, sig, w.perm, delta0, rmax, scal, &rank_s);
+    if (threadIdx.x == 0) w.fr[k] = rank;
+    // F = kept columns of W (r0 x rank); Y = Q [V_kept; 0] (nc x rank)
+    double *Y = work;
+    for (int64_t e = threadIdx.x; e < (int64_t)r0 * rank; e += WG) {
+      const int a = (int)(e % r0), l = (int)(e / r0);
+      F[e] = X[a + (int64_t)nb * w.perm[l]];
+    }
+    for (int64_t e = threadIdx.x; e < (int64_t)mb * rank; e += WG) {
+      const int i = (int)(e % mb), l = (int)(e / mb);
+      Y[e] = (i < nb) ? Vv[i + (int64_t)nb * w.perm[l]] : 0.0;
+    }
+    __syncthreads();
+    apply_q(Bq, mb, nb, tau, Y, rank);
+    for (int64_t e = threadIdx.x; e < (int64_t)rank * nc; e += WG) {
+      const int l = (int)(e % rank), col = (int)(e / rank);
+      core0[e] = Y[col + (int64_t)mb * l];
+    }
+    return;
+  }
   // B and V both in LDS, or B in LDS with the rotations logged and replayed
   // onto V in the same LDS afterwards, or both in global memory
   const bool both = LDS && (int64_t)mb * nb + (int64_t)nb * nb <= LDS_DBL;
@@ -671,7 +740,8 @@ hipError_t round_tt(const TTView &x, double eps, int rmax, const RoundWs &w,
     const int64_t ncc = (int64_t)x.n[k] * x.m[k] * frc;
     const int64_t nbc = r0c < ncc ? r0c : ncc;
     const int64_t mbc = r0c > ncc ? r0c : ncc;
-    if (mbc * nbc <= LDS_DBL && nbc * nbc <= LDS_DBL)
+    const bool wide_qr = r0c < ncc && mbc * nbc + 2 * nbc * nbc <= LDS_SVD;
+    if ((mbc * nbc <= LDS_DBL && nbc * nbc <= LDS_DBL) || wide_qr)
       hipLaunchKernelGGL(k_svd_step<true>, dim3(1), dim3(WG), 0, s, x, k, eps, rmax,
                          w.carry, w.work, w.vbuf, w.fold, sig, w.iwork, w.scal, w.rotlog);
     else
