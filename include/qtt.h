@@ -338,6 +338,52 @@ qtt_status qtt_matvec_round_batched(int32_t n, qtt_matvec_round_case *cases, int
                                     void *const *ws, const size_t *ws_bytes,
                                     void *const *streams);
 
+/* ------------------------------------------------------------ warm start */
+/* A multilayer perceptron from load parameters to the QTT cores of the
+ * displacement (the learned warm start of the solve; not in the paper).
+ * sizes[0] inputs, sizes[1..nlayers-1] hidden widths with ReLU,
+ * sizes[nlayers] outputs = the packed size of the train's rank pattern.
+ * params holds, layer after layer, W_l (sizes[l+1] x sizes[l], column-major)
+ * then b_l; adam_m and adam_v have the same layout.  FP32, device memory,
+ * caller-owned.  step counts the Adam steps taken.                         */
+typedef struct {
+  int32_t nlayers;
+  const int32_t *sizes;   /* host, nlayers + 1 entries */
+  float *params;
+  float *adam_m, *adam_v; /* training only (may be NULL for inference) */
+  int64_t step;
+} qtt_mlp;
+
+/* Number of floats in params for these layer sizes (-1 on bad input).      */
+int64_t qtt_mlp_param_count(int32_t nlayers, const int32_t *sizes);
+
+/* Workspace bytes for a batch (ncores = 0: inference only; otherwise the
+ * train's modes nrow[ncores], rank pattern ranks[ncores + 1] and the
+ * optional metric of qtt_warmstart_train_step).                            */
+qtt_status qtt_warmstart_workspace(const qtt_mlp *net, int32_t batch, int32_t ncores,
+                                   const int32_t *nrow, const int32_t *ranks,
+                                   const qtt_tt *metric, size_t *bytes);
+
+/* qtt_warmstart_infer — out (sizes[nlayers] x batch, column-major, device)
+ * = MLP(a) for a (sizes[0] x batch); each column is the packed train.      */
+qtt_status qtt_warmstart_infer(const qtt_mlp *net, const float *a, int32_t batch, float *out,
+                               void *ws, size_t ws_bytes, void *stream);
+
+/* qtt_warmstart_train_step — one Adam step (learning rate lr) on the mean
+ * over the batch of the gauge-invariant loss ||TT(o_j) - u_j||^2/||u_j||^2,
+ * where o_j = MLP(a_j) and u_j (column j of targets, packed with the same
+ * rank pattern, zero-padded) is the target train: forward pass, loss and
+ * gradient through the TT inner products (FP64 environments), backward
+ * pass, Adam.  With metric (a symmetric positive definite QTT matrix with
+ * the train's modes, FP64, e.g. the stiffness matrix) the norm is the
+ * energy norm ||v||_A^2 = <v, A v> (three-operand environments); metric
+ * NULL: the Frobenius norm.  *loss receives the batch's mean loss before
+ * the step.  Synchronises `stream`.                                         */
+qtt_status qtt_warmstart_train_step(qtt_mlp *net, const float *a, const float *targets,
+                                    int32_t batch, int32_t ncores, const int32_t *nrow,
+                                    const int32_t *ranks, const qtt_tt *metric, float lr,
+                                    double *loss, void *ws, size_t ws_bytes, void *stream);
+
 /* Thread-local text of the last error of this thread.                      */
 const char *qtt_last_error(void);
 

@@ -10,4 +10,5 @@ from ._lib import (  # noqa: F401
     matvec, matvec_round, matvec_round_workspace, round_, round_sketch, dot, axpby, assemble, assemble_bpx, solve, solve_workspace_bytes,
     tt_from_cores, tt_to_cores, problem_from_workload, version,
     Batch, solve_batched, autotune_batched, StepBatch, matvec_round_batched,
+    MLP, columns, tt_from_packed,
 )

@@ -68,6 +68,12 @@ class _SolveCase(C.Structure):
                 ("ws_bytes", C.c_size_t), ("stream", C.c_void_p), ("status", C.c_int32)]
 
 
+class _MLP(C.Structure):
+    _fields_ = [("nlayers", C.c_int32), ("sizes", C.POINTER(C.c_int32)),
+                ("params", C.c_void_p), ("adam_m", C.c_void_p), ("adam_v", C.c_void_p),
+                ("step", C.c_int64)]
+
+
 class _MVRCase(C.Structure):
     _fields_ = [("A", C.POINTER(_TT)), ("x", C.POINTER(_TT)), ("y", C.POINTER(_TT)),
                 ("compute", C.c_int32), ("ell", C.c_int32), ("seed", C.c_uint64),
@@ -111,6 +117,14 @@ def load_library(path: str = LIB_PATH):
                             vp, sz, vp]
     L.qtt_solve_workspace.argtypes = [P(_TT), P(_TT), P(_SolveOpts), P(sz)]
     L.qtt_solve_batched.argtypes = [C.c_int32, P(_SolveCase), C.c_int32]
+    L.qtt_mlp_param_count.argtypes = [C.c_int32, P(C.c_int32)]
+    L.qtt_mlp_param_count.restype = C.c_int64
+    L.qtt_warmstart_workspace.argtypes = [P(_MLP), C.c_int32, C.c_int32, P(C.c_int32),
+                                          P(C.c_int32), P(_TT), P(sz)]
+    L.qtt_warmstart_infer.argtypes = [P(_MLP), vp, C.c_int32, vp, vp, sz, vp]
+    L.qtt_warmstart_train_step.argtypes = [P(_MLP), vp, vp, C.c_int32, C.c_int32, P(C.c_int32),
+                                           P(C.c_int32), P(_TT), C.c_float, P(C.c_double), vp,
+                                           sz, vp]
     L.qtt_matvec_round_batched.argtypes = [C.c_int32, P(_MVRCase), C.c_int32, P(vp), P(sz),
                                            P(vp)]
     L.qtt_autotune_batched.argtypes = [C.c_int32, P(_SolveCase), P(C.c_int32), P(C.c_double)]
@@ -119,7 +133,8 @@ def load_library(path: str = LIB_PATH):
                  "qtt_dot", "qtt_axpby",
                  "qtt_assemble_stiffness", "qtt_assemble_workspace", "qtt_assemble_bpx", "qtt_solve",
                  "qtt_solve_workspace", "qtt_solve_batched", "qtt_autotune_batched",
-                 "qtt_matvec_round_batched"):
+                 "qtt_matvec_round_batched", "qtt_warmstart_workspace", "qtt_warmstart_infer",
+                 "qtt_warmstart_train_step"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -549,3 +564,74 @@ def matvec_round_batched(batch: StepBatch):
     _check(lib().qtt_matvec_round_batched(batch.n, batch.cases, batch.nworkers, batch.ws_ptr,
                                           batch.ws_len, batch.st_ptr))
     return batch.outputs()
+
+
+class MLP:
+    """The warm-start network: FP32 parameters and Adam moments in device
+    memory (layout of qtt_mlp), initial values given by the caller."""
+
+    def __init__(self, sizes, params):
+        torch = _torch()
+        self.sizes = [int(v) for v in sizes]
+        self._sizes = (C.c_int32 * len(self.sizes))(*self.sizes)
+        n = lib().qtt_mlp_param_count(len(self.sizes) - 1, self._sizes)
+        flat = np.asarray(params, dtype=np.float32).reshape(-1)
+        if flat.size != n:
+            raise ValueError("expected %d parameters, got %d" % (n, flat.size))
+        self.params = torch.from_numpy(flat.copy()).to("cuda")
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.c = _MLP(len(self.sizes) - 1, self._sizes, self.params.data_ptr(),
+                      self.m.data_ptr(), self.v.data_ptr(), 0)
+
+    def infer(self, a):
+        """a: (nin, B) array -> (nout, B) float32 tensor on the device."""
+        torch = _torch()
+        at = torch.as_tensor(np.asarray(a, dtype=np.float32), device="cuda").t().contiguous().t()
+        B = at.shape[1]
+        out = torch.empty((B, self.sizes[-1]), dtype=torch.float32, device="cuda")
+        need = C.c_size_t()
+        _check(lib().qtt_warmstart_workspace(C.byref(self.c), B, 0, None, None, None,
+                                             C.byref(need)))
+        ws = _workspace(need.value)
+        _check(lib().qtt_warmstart_infer(C.byref(self.c), C.c_void_p(at.data_ptr()), B,
+                                         C.c_void_p(out.data_ptr()),
+                                         C.c_void_p(_aligned_ptr(ws)), ws.numel() - 256,
+                                         _stream_ptr()))
+        return out.t()
+
+    def train_step(self, a, targets, nrow, ranks, lr: float, metric: Optional["TT"] = None) -> float:
+        """a: (nin, B) and targets (nout, B) float32 device tensors with
+        column-major storage (B rows of the transposed tensor); metric: the
+        energy-norm operator (None: Frobenius norm)."""
+        mp = C.byref(metric.c) if metric is not None else None
+        B = a.shape[1]
+        D = len(nrow)
+        nr = (C.c_int32 * D)(*nrow)
+        rk = (C.c_int32 * (D + 1))(*ranks)
+        need = C.c_size_t()
+        _check(lib().qtt_warmstart_workspace(C.byref(self.c), B, D, nr, rk, mp, C.byref(need)))
+        if getattr(self, "_ws", None) is None or self._ws.numel() < need.value + 256:
+            self._ws = _workspace(need.value)
+        loss = C.c_double()
+        _check(lib().qtt_warmstart_train_step(C.byref(self.c), C.c_void_p(a.data_ptr()),
+                                              C.c_void_p(targets.data_ptr()), B, D, nr, rk, mp,
+                                              float(lr), C.byref(loss),
+                                              C.c_void_p(_aligned_ptr(self._ws)),
+                                              self._ws.numel() - 256, _stream_ptr()))
+        return loss.value
+
+
+def columns(x: np.ndarray):
+    """(n, B) array -> float32 device tensor whose storage is column-major
+    (one sample after another), the layout of the warm-start calls."""
+    torch = _torch()
+    return torch.as_tensor(np.ascontiguousarray(np.asarray(x, dtype=np.float32).T),
+                           device="cuda").t()
+
+
+def tt_from_packed(col, nrow, ranks) -> TT:
+    """A packed train (one output column of the network) as an FP64 TT."""
+    torch = _torch()
+    data = col.to(torch.float64).contiguous()
+    return TT(list(nrow), None, list(ranks), data.numel(), data)

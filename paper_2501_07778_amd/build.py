@@ -27,6 +27,7 @@ SOURCES = [
     "k_sketch.hip",
     "k_full.hip",
     "batched.cpp",
+    "k_mlp.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
