@@ -42,6 +42,11 @@ def _parse():
     ap.add_argument("--level", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="only launch the level-10 product 5 times and a plain 423 MB device "
+                         "copy 5 times (for hardware counter passes), print their sizes, exit")
+    ap.add_argument("--no-solve", dest="solve", action="store_false",
+                    help="skip the level-5 solve measurement")
     ap.add_argument("--batch", type=int, default=64,
                     help="cases of the batched-step measurement (0: skip)")
     return ap.parse_args()
@@ -68,6 +73,25 @@ def step(P, K, x, y, ws, seed, compute="f64"):
     return y
 
 
+def measured_traffic():
+    """HBM bytes per launch of k_matvec_f64 from the committed counter
+    summary, or None once the kernel source has changed since."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    summ = os.path.join(here, "profiles", "k_matvec_f64_level10_pmc.md")
+    src = os.path.join(here, "paper_2501_07778_amd", "csrc", "k_tt.hip")
+    try:
+        txt = open(summ).read()
+        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in txt.splitlines() if ": " in line and
+                (line.startswith("traffic_bytes") or line.startswith("source_sha1")))
+    if vals.get("source_sha1(paper_2501_07778_amd/csrc/k_tt.hip)", "").strip() != sha:
+        return None
+    return int(vals["traffic_bytes_per_launch"])
+
+
 def matvec_roofline(P, torch, K, x):
     """k_matvec_f64 alone: HIP events on the stream it is launched on."""
     y = P.matvec(K, x)
@@ -86,7 +110,7 @@ def matvec_roofline(P, torch, K, x):
     nbytes = tt_bytes(K) + tt_bytes(x) + tt_bytes(y)
     gbs = nbytes / (ms * 1e-3) / 1e9
     return dict(kernel="k_matvec_f64", bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS,
-                unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,
+                unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
                 bytes_per_launch=nbytes, ms_per_launch=round(ms, 4))
 
 
@@ -156,6 +180,30 @@ def batched_steps(P, torch, ncases: int):
                 speedup_vs_1_worker=round(rates[1] / rates[best], 2))
 
 
+def small_solve(P, torch, level: int):
+    """The plain-method configuration: level-5 unit square, left edge
+    clamped, body force (0, -1), eps 1e-10: BPX-preconditioned flexible CG
+    to a preconditioned residual of 1e-10; solves/s of one solve after a
+    warm-up solve, and the solver's FP64 dense residual."""
+    import workloads as W
+    prob = W.cantilever_body_force(level)
+    K, f = P.assemble(prob)
+    C = P.assemble_bpx(prob)
+    opts = P.SolveOpts(tol=1e-10, eps=1e-10, rmax=64, eps_in=1e-3, rmax_in=32, maxit_in=1000,
+                       check_every=10, precond=C, sketch=8, seed=1, method="fcg")
+    ws = P._lib._workspace(P.solve_workspace_bytes(K, f, opts))
+    P.solve(K, f, opts, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, rep = P.solve(K, f, opts, ws=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dict(workload="unit square level %d (%d dofs), body force, eps 1e-10, BPX + flexible CG"
+                % (level, 2 * 4 ** level), solves_per_s=round(1.0 / dt, 4),
+                ms_per_solve=round(1e3 * dt, 1), iterations=rep["inner"], status=rep["status"],
+                fp64_residual=float("%.3e" % rep["residual"]), solution_max_rank=rep["max_rank"])
+
+
 def cpu_baseline(level, nbytes, seconds):
     """The FP64 oracle's product and exact rounding of the same workload;
     a bounded sample: the product of all cores, then the rounding of the
@@ -215,6 +263,21 @@ def main():
     import paper_2501_07778_amd as P
 
     prob, K, x = workload(args.level)
+    if args.pmc_probe:
+        y = P.matvec(K, x)
+        src = torch.empty(y.numel(), dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            P.matvec(K, x, y=y)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"matvec_bytes_algorithmic": tt_bytes(K) + tt_bytes(x) + tt_bytes(y),
+                          "matvec_write_bytes": tt_bytes(y),
+                          "copy_read_bytes": 8 * src.numel(), "copy_write_bytes": 8 * dst.numel()}),
+              flush=True)
+        return
     y = None
     ws = P.matvec_round_workspace(K, x, ELL)
     for i in range(args.warmup):
@@ -233,6 +296,7 @@ def main():
     roof = matvec_roofline(P, torch, K, x)
     mixed = mixed_precision(P, torch, K, x, ws, max(2, args.steps // 2))
     batched = batched_steps(P, torch, args.batch) if args.batch > 0 else None
+    solve5 = small_solve(P, torch, 5) if args.solve else None
     line = {
         "metric": "QTT solves/sec and matvec+round GB/s at rel. err 1e-6 vs FP64 plain GPU",
         "value": round(value, 3),
@@ -252,7 +316,7 @@ def main():
                                % (args.level, 2 * 4 ** args.level, K.D, max(K.ranks), RANK,
                                   EPS, RANK, ELL),
                    "bytes_per_step": nbytes, "result_ranks_max": max(y.ranks),
-                   "mixed_precision": mixed, "batched_steps": batched},
+                   "mixed_precision": mixed, "batched_steps": batched, "solve_level5": solve5},
         "roofline": roof,
     }
     if not args.no_cpu:
