@@ -92,6 +92,9 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError("libqtt.so not built: run `python -m paper_2501_07778_amd.build` "
                           "(expected at %s)" % path)
+    # torch first: its HIP runtime must be the one libqtt.so binds to, so that
+    # both share one runtime (and one set of devices and streams)
+    _torch()
     L = C.CDLL(path)
     P = C.POINTER
     vp, sz = C.c_void_p, C.c_size_t

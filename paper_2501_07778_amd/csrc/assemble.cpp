@@ -926,6 +926,7 @@ extern "C" qtt_status qtt_assemble_workspace(const qtt_problem *p, size_t *bytes
 extern "C" qtt_status qtt_assemble_stiffness(const qtt_problem *p, double eps, qtt_tt *K,
                                              qtt_tt *f, void *ws, size_t ws_bytes,
                                              void *stream) {
+  qtt::clear_stale_error();
   qtt_status st = check_problem(p);
   if (st != QTT_OK) return st;
   if (!K || !f || !K->data || !f->data || !K->ranks || !f->ranks)
@@ -989,6 +990,7 @@ extern "C" qtt_status qtt_assemble_stiffness(const qtt_problem *p, double eps, q
 
 extern "C" qtt_status qtt_assemble_bpx(const qtt_problem *p, double eps, qtt_tt *C, void *ws,
                                        size_t ws_bytes, void *stream) {
+  qtt::clear_stale_error();
   qtt_status st = check_problem(p);
   if (st != QTT_OK) return st;
   if (p->q != 1) return fail(QTT_E_UNSUPPORTED, "the BPX preconditioner is built for q = 1");

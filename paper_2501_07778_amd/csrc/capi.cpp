@@ -131,6 +131,7 @@ const char *qtt_version(void) { return "qtt-mi355x 0.1 (gfx950)"; }
 qtt_status qtt_matvec(const qtt_tt *A, const qtt_tt *x, qtt_tt *y,
                       qtt_dtype compute, void *ws, size_t ws_bytes,
                       void *stream) {
+  qtt::clear_stale_error();
   qtt_status st;
   if ((st = check_tt(A, "A", true)) != QTT_OK) return st;
   if ((st = check_tt(x, "x", true)) != QTT_OK) return st;
@@ -189,6 +190,7 @@ qtt_status qtt_round_workspace(const qtt_tt *x, int32_t rmax, size_t *bytes) {
 
 qtt_status qtt_round(qtt_tt *x, double eps, int32_t rmax, double *norm,
                      double *err, void *ws, size_t ws_bytes, void *stream) {
+  qtt::clear_stale_error();
   qtt_status st;
   if ((st = check_tt(x, "x", true)) != QTT_OK) return st;
   if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(QTT_E_INVAL, "eps must be >= 0");
@@ -248,6 +250,7 @@ qtt_status qtt_round_sketch_workspace(const qtt_tt *x, int32_t ell, size_t *byte
 qtt_status qtt_round_sketch(qtt_tt *x, int32_t ell, uint64_t seed, double eps, int32_t rmax,
                             double *norm, double *err, void *ws, size_t ws_bytes,
                             void *stream) {
+  qtt::clear_stale_error();
   qtt_status st;
   if ((st = check_tt(x, "x", true)) != QTT_OK) return st;
   if (x->ncol) return fail(QTT_E_INVAL, "x must be a vector");
@@ -334,6 +337,7 @@ qtt_status qtt_matvec_round_workspace(const qtt_tt *A, const qtt_tt *x, int32_t 
 qtt_status qtt_matvec_round(const qtt_tt *A, const qtt_tt *x, qtt_tt *y, qtt_dtype compute,
                             int32_t ell, uint64_t seed, double eps, int32_t rmax, double *norm,
                             double *err, void *ws, size_t ws_bytes, void *stream) {
+  qtt::clear_stale_error();
   qtt_status st;
   if ((st = check_matvec_args(A, x, compute)) != QTT_OK) return st;
   if (!y || !y->ranks || !y->nrow || !y->data) return fail(QTT_E_INVAL, "y: NULL field");
@@ -389,6 +393,7 @@ qtt_status qtt_matvec_round(const qtt_tt *A, const qtt_tt *x, qtt_tt *y, qtt_dty
 
 qtt_status qtt_dot(const qtt_tt *x, const qtt_tt *y, double *out, void *ws,
                    size_t ws_bytes, void *stream) {
+  qtt::clear_stale_error();
   qtt_status st;
   if ((st = check_tt(x, "x", true)) != QTT_OK) return st;
   if ((st = check_tt(y, "y", true)) != QTT_OK) return st;
@@ -423,6 +428,7 @@ qtt_status qtt_dot(const qtt_tt *x, const qtt_tt *y, double *out, void *ws,
 
 qtt_status qtt_axpby(double a, const qtt_tt *x, double b, const qtt_tt *y,
                      qtt_tt *z, void *ws, size_t ws_bytes, void *stream) {
+  qtt::clear_stale_error();
   qtt_status st;
   if ((st = check_tt(x, "x", true)) != QTT_OK) return st;
   if ((st = check_tt(y, "y", true)) != QTT_OK) return st;

@@ -32,6 +32,11 @@ struct TTView {
 };
 
 // ---------------------------------------------------------------- errors
+// Entry points that launch kernels start by clearing HIP's per-thread last
+// error: a failed runtime call made earlier by another library in the same
+// thread would otherwise be reported by the first launch check.
+inline void clear_stale_error() { (void)hipGetLastError(); }
+
 void set_error(const std::string &msg);
 qtt_status fail(qtt_status st, const std::string &msg);
 #define QTT_HIP(call)                                                     \

@@ -563,6 +563,7 @@ extern "C" qtt_status qtt_warmstart_workspace(const qtt_mlp *net, int32_t batch,
 
 extern "C" qtt_status qtt_warmstart_infer(const qtt_mlp *net, const float *a, int32_t batch,
                                           float *out, void *ws, size_t ws_bytes, void *stream) {
+  qtt::clear_stale_error();
   qtt_status st = check_net(net);
   if (st != QTT_OK) return st;
   if (!a || !out || batch < 1) return fail(QTT_E_INVAL, "a, out and batch >= 1 required");
@@ -585,6 +586,7 @@ extern "C" qtt_status qtt_warmstart_train_step(qtt_mlp *net, const float *a, con
                                                const int32_t *ranks, const qtt_tt *metric,
                                                float lr, double *loss, void *ws, size_t ws_bytes,
                                                void *stream) {
+  qtt::clear_stale_error();
   qtt_status st = check_net(net);
   if (st != QTT_OK) return st;
   if (!a || !targets || batch < 1) return fail(QTT_E_INVAL, "a, targets and batch >= 1 required");

@@ -330,49 +330,52 @@ __device__ int jacobi(double *B, int mb, int nb, double *V, double *rot_log, int
     __syncthreads();
     for (int r = 0; r < N - 1; ++r) {
       double *lg = rot_log ? rot_log + 2 * ((int64_t)(sweep * (N - 1) + r) * (N / 2)) : nullptr;
-      for (int i = grp; i < N / 2; i += NGRP) {
+      // every group runs the same number of passes (idle groups sum zeros)
+      for (int i0 = 0; i0 < N / 2; i0 += NGRP) {
+        const int i = i0 + grp;
         int p = (r + i) % (N - 1);
         int q = (i == 0) ? (N - 1) : (r - i + N - 1) % (N - 1);
-        double c = 1.0, sn = 0.0;
-        if (p < nb && q < nb) {
-          if (p > q) { int t = p; p = q; q = t; }
-          double *bp = B + (int64_t)mb * p, *bq = B + (int64_t)mb * q;
-          double al = 0.0, be = 0.0, ga = 0.0;
+        const bool act = i < N / 2 && p < nb && q < nb;
+        if (p > q) { int t = p; p = q; q = t; }
+        double *bp = B + (int64_t)mb * (act ? p : 0), *bq = B + (int64_t)mb * (act ? q : 0);
+        double al = 0.0, be = 0.0, ga = 0.0;
+        if (act) {
           for (int l = gl; l < mb; l += GL) {
             const double u = bp[l], v = bq[l];
             al = fma(u, u, al);
             be = fma(v, v, be);
             ga = fma(u, v, ga);
           }
-          al = group_sum(al);
-          be = group_sum(be);
-          ga = group_sum(ga);
-          if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-            const double zeta = (be - al) / (2.0 * ga);
-            double t;
-            if (fabs(zeta) > 1e150)
-              t = 0.5 / zeta;
-            else
-              t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            c = 1.0 / sqrt(1.0 + t * t);
-            sn = c * t;
-            for (int l = gl; l < mb; l += GL) {
-              const double u = bp[l], v = bq[l];
-              bp[l] = c * u - sn * v;
-              bq[l] = sn * u + c * v;
-            }
-            if (V) {
-              double *vp = V + (int64_t)nb * p, *vq = V + (int64_t)nb * q;
-              for (int l = gl; l < nb; l += GL) {
-                const double u = vp[l], v = vq[l];
-                vp[l] = c * u - sn * v;
-                vq[l] = sn * u + c * v;
-              }
-            }
-            if (gl == 0) *flag = 1;
-          }
         }
-        if (lg && gl == 0) {
+        al = group_sum(al);
+        be = group_sum(be);
+        ga = group_sum(ga);
+        double c = 1.0, sn = 0.0;
+        if (act && ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          double t;
+          if (fabs(zeta) > 1e150)
+            t = 0.5 / zeta;
+          else
+            t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          c = 1.0 / sqrt(1.0 + t * t);
+          sn = c * t;
+          for (int l = gl; l < mb; l += GL) {
+            const double u = bp[l], v = bq[l];
+            bp[l] = c * u - sn * v;
+            bq[l] = sn * u + c * v;
+          }
+          if (V) {
+            double *vp = V + (int64_t)nb * p, *vq = V + (int64_t)nb * q;
+            for (int l = gl; l < nb; l += GL) {
+              const double u = vp[l], v = vq[l];
+              vp[l] = c * u - sn * v;
+              vq[l] = sn * u + c * v;
+            }
+          }
+          if (gl == 0) *flag = 1;
+        }
+        if (lg && gl == 0 && i < N / 2) {
           lg[2 * i] = c;
           lg[2 * i + 1] = sn;
         }

@@ -260,6 +260,7 @@ extern "C" qtt_status qtt_solve_workspace(const qtt_tt *K, const qtt_tt *f,
 extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
                                 const qtt_solve_opts *o, qtt_tt *u, qtt_solve_report *rep,
                                 void *ws, size_t ws_bytes, void *stream) {
+  qtt::clear_stale_error();
   qtt_status st;
   if ((st = check_system(K, f)) != QTT_OK) return st;
   if ((st = check_opts(o)) != QTT_OK) return st;

@@ -73,6 +73,7 @@ def test_matvec_low_precision(P, compute, tol):
     ([2] * 8, 70, 1e-12, 0),                 # unfoldings larger than a tile
     ([2] * 16, 128, 1e-10, 0),               # Jacobi with logged rotations replayed
     ([2] * 16, 128, 1e-3, 40),
+    ([2] * 12, 200, 1e-9, 0),                # global-memory Jacobi, > 64 pairs per round
 ])
 def test_round_matches_oracle(P, modes, r, eps, rmax):
     y = _vec(7, modes, r)
