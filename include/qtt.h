@@ -201,9 +201,12 @@ typedef enum {
   QTT_SOLVE_CG_IR = 0,     /* truncated CG with FP64 iterative refinement      */
   QTT_SOLVE_CHEBYSHEV = 1, /* preconditioned Chebyshev iteration, true residual
                               every step (needs `precond`)                      */
-  QTT_SOLVE_FCG = 2        /* flexible preconditioned CG (one stored direction),
+  QTT_SOLVE_FCG = 2,       /* flexible preconditioned CG (one stored direction),
                               true residual every step, exact step length
                               (needs `precond`)                                */
+  QTT_SOLVE_ALS = 3        /* one-site alternating least squares at fixed
+                              ranks: the core update of the paper's AMEn
+                              solver (Sec. 4) without residual enrichment   */
 } qtt_solve_method;
 
 typedef struct {
@@ -265,6 +268,18 @@ typedef struct {
  * the energy error decreases at every step whatever the truncation of z and
  * p (Notay's flexible CG with one stored direction); r = round(f - K u) is
  * recomputed from the iterate; stop as CHEBYSHEV.
+ * ALS: one-site alternating least squares at fixed ranks (the bounded caps
+ * of rmax): each core in turn minimises the energy <u, K u>/2 - <u, f>
+ * with the other cores fixed and orthogonal (a dense SPD local system of
+ * r_k n_k r_{k+1} unknowns solved by Cholesky), sweeping left-right and back;
+ * stop when the energy decrease over a sweep, relative to |energy|, is
+ * <= tol^2 (criterion = its square root, one entry of residual_hist per
+ * sweep), at most maxit_out sweeps; eps > 0 then rounds u (exact rounding).
+ * Local systems, QR and the final residual are FP64 (compute must be
+ * QTT_F64); precond, eps_in, rmax_in, red_in, maxit_in, check_every and
+ * sketch are unused; seed selects the random start cores when x0 is NULL
+ * (x0 is zero-padded to the ranks).  The workspace holds one local matrix
+ * (8 (r n r)^2 bytes at the widest core).  rmax <= 512.
  * CHEBYSHEV: u_{k+1} = u_k + d_k with d_k = c1 d_{k-1} + c2 round(C r_k),
  * r_k = round(f - K u_k) recomputed from u_k at every step (so rounding
  * errors do not accumulate in a recurrence), c1, c2 from the Chebyshev

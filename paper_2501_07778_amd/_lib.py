@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libqtt.so")
 
 QTT_F64, QTT_F32, QTT_BF16 = 0, 1, 2
 _DTYPES = {"f64": QTT_F64, "f32": QTT_F32, "bf16": QTT_BF16}
-_METHODS = {"cg": 0, "chebyshev": 1, "fcg": 2}
+_METHODS = {"cg": 0, "chebyshev": 1, "fcg": 2, "als": 3}
 MAX_CORES = 40
 
 
@@ -413,7 +413,7 @@ class SolveOpts:
     sketch: int = 0
     seed: int = 0
     precond: Optional["TT"] = None
-    method: str = "cg"          # "cg" (CG with refinement), "chebyshev" or "fcg"
+    method: str = "cg"          # "cg" (CG with refinement), "chebyshev", "fcg" or "als"
     lmin: float = 0.0
     lmax: float = 0.0
 
@@ -446,16 +446,16 @@ def solve(K: TT, f: TT, opts: SolveOpts, x0: Optional[TT] = None, ws=None):
                          C.c_void_p(_aligned_ptr(ws)), ws.numel() - 256, _stream_ptr())
     if st not in (0, -4):
         _check(st)
-    nh = rep.outer + 1 if opts.method == "cg" else rep.inner // max(opts.check_every, 1) + 1
-    report = dict(status=rep.status, outer=rep.outer, inner=rep.inner,
-                  residual=rep.residual,
-                  residual_hist=[rep.residual_hist[i] for i in range(min(nh, 64))],
-                  max_rank=rep.max_rank, criterion=rep.criterion, lmax=rep.lmax)
-    return u, report
+    return u, _report_dict(rep, opts)
 
 
 def _report_dict(rep, opts):
-    nh = rep.outer + 1 if opts.method == "cg" else rep.inner // max(opts.check_every, 1) + 1
+    if opts.method == "cg":
+        nh = rep.outer + 1
+    elif opts.method == "als":
+        nh = rep.outer            # energy decrease of each sweep
+    else:
+        nh = rep.inner // max(opts.check_every, 1) + 1
     return dict(status=rep.status, outer=rep.outer, inner=rep.inner, residual=rep.residual,
                 residual_hist=[rep.residual_hist[i] for i in range(min(nh, 64))],
                 max_rank=rep.max_rank, criterion=rep.criterion, lmax=rep.lmax)

@@ -22,9 +22,11 @@ SOURCES = [
     "capi.cpp",
     "assemble.cpp",
     "solve.cpp",
+    "als.cpp",
     "k_tt.hip",
     "k_round.hip",
     "k_sketch.hip",
+    "k_als.hip",
     "k_full.hip",
     "batched.cpp",
     "k_mlp.hip",

@@ -165,4 +165,45 @@ hipError_t launch_diff_norm2(const double *a, const double *b, int64_t n, double
 hipError_t upload_ranks(const TTView &v, const int32_t *ranks,
                         hipStream_t s);
 
+// ---------------------------------------------------------------- ALS
+// Kernels of the one-site ALS solve (k_als.hip); all dimensions are host
+// values, cores column-major as above, environments P[a, al, a'] (vector
+// rank, operator rank, vector rank) and Q[a, c] (vector rank, load rank).
+hipError_t als_env3_left(const double *P, const double *X, const double *A, const double *Y,
+                         double *Pn, double *W1, double *W2, int r0, int ra0, int n, int ra1,
+                         int r1, hipStream_t s);
+hipError_t als_env3_right(const double *Pn, const double *X, const double *A, const double *Y,
+                          double *P, double *W1, double *W2, int r0, int ra0, int n, int ra1,
+                          int r1, hipStream_t s);
+hipError_t als_env2_left(const double *Q, const double *X, const double *F, double *Qn,
+                         double *Tm, int r0, int rf0, int n, int r1, int rf1, hipStream_t s);
+hipError_t als_env2_right(const double *Qn, const double *X, const double *F, double *Q,
+                          double *Tm, int r0, int rf0, int n, int r1, int rf1, hipStream_t s);
+// B (N x N, N = r0 n r1) and g (N) of the local system of one core; T holds
+// r0^2 n^2 ra1 doubles
+hipError_t als_local_system(const double *L, const double *K, const double *R, const double *Lf,
+                            const double *F, const double *Rf, double *T, double *B, double *g,
+                            int r0, int ra0, int n, int ra1, int r1, int rf0, int rf1,
+                            hipStream_t s);
+// B y = g for SPD B: B is overwritten by its Cholesky factor, g by y;
+// *flag becomes nonzero on a pivot <= 0
+hipError_t als_cholesky_solve(double *B, int64_t N, double *g, int *flag, hipStream_t s);
+// thin Householder QR of W (rows x cols, cols <= rows): Q -> W, R -> R
+hipError_t als_qr(double *W, int rows, int cols, double *R, double *tau, hipStream_t s);
+hipError_t als_gemm(const double *A, int lda, const double *B, int ldb, bool tb, double *C, int ldc,
+                    int M, int N, int K, hipStream_t s);
+hipError_t als_fill(double *x, int64_t n, uint64_t seed, double scale, hipStream_t s);
+hipError_t als_fill_value(double *x, int64_t n, double v, hipStream_t s);
+hipError_t als_vdot(const double *a, const double *b, int64_t n, double *out, hipStream_t s);
+hipError_t als_transpose(const double *src, int rows, int cols, double *dst, hipStream_t s);
+hipError_t als_pad_core(const double *src, int r0s, int n, int r1s, double *dst, int r0d, int r1d,
+                        hipStream_t s);
+
+// the ALS method of qtt_solve (als.cpp)
+qtt_status check_als_opts(const qtt_solve_opts *o);
+size_t als_workspace_bytes(const qtt_tt *K, const qtt_tt *f, const qtt_solve_opts *o);
+qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
+                     const qtt_solve_opts *o, qtt_tt *u, qtt_solve_report *rep, void *ws,
+                     size_t ws_bytes, hipStream_t s);
+
 }  // namespace qtt

@@ -1,0 +1,650 @@
+// k_als.hip — alternating least squares (one-site ALS) on the QTT format,
+// gfx950: the solve that works on the cores of the solution instead of
+// rounding global residuals (the approach of the AMEn family the paper uses,
+// without the residual enrichment; Holtz, Rohwedder and Schneider, SIAM J.
+// Sci. Comput. 2012).
+//
+// With the cores left of k left-orthogonal and right of k right-orthogonal,
+// core k minimises the energy <x, K x>/2 - <x, f> exactly by solving the
+// projected system B y = g, where
+//   B[(a,i,b),(a',j,b')] = sum_{al,be} L[a,al,a'] K_k[al,i,j,be] R[b,be,b'],
+//   g[(a,i,b)]           = sum_{c,d} Lf[a,c] F_k[c,i,d] Rf[b,d],
+// with L/R the left/right environments of <x, K x> and Lf/Rf those of <x, f>.
+// B is symmetric positive definite (K is, the frames are orthonormal); it is
+// factored by a blocked right-looking Cholesky (64-wide panels: panel
+// factorisation in one workgroup, triangular solve of the panel rows, a
+// tiled trailing update).  After the solve the core is orthogonalised (QR)
+// and the environment moves one core on.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "internal.h"
+
+namespace qtt {
+namespace {
+
+constexpr int CB = 64;       // Cholesky panel width
+constexpr int AWG = 256;
+
+// ---------------------------------------------------------------- envs
+// Environments are contracted in three (or two) grid-stride stages, each a
+// plain sum over one or two indices; every stage writes its whole result.
+//
+// left step of <x, A y>: P'[b, be, b'] = sum X[a,i,b] A[al,i,j,be] Y[a',j,b'] P[a,al,a']
+// stage 1: W1[a, al, j, b'] = sum_a' P[a, al, a'] Y[a', j, b']
+__global__ void k_e3l_1(const double *P, const double *Y, double *W1, int r0, int ra0, int n,
+                        int r1) {
+  const int64_t ne = (int64_t)r0 * ra0 * n * r1, ra = (int64_t)r0 * ra0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t aal = e % ra, jb = e / ra;
+    const double *yc = Y + (int64_t)r0 * jb;
+    double acc = 0.0;
+    for (int a2 = 0; a2 < r0; ++a2) acc = fma(P[aal + ra * a2], yc[a2], acc);
+    W1[e] = acc;
+  }
+}
+// stage 2: W2[a, i, be, b'] = sum_{j, al} W1[a, al, j, b'] A[al, i, j, be]
+__global__ void k_e3l_2(const double *W1, const double *A, double *W2, int r0, int ra0, int n,
+                        int ra1, int r1) {
+  const int64_t ne = (int64_t)r0 * n * ra1 * r1;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e % r0);
+    int64_t t = e / r0;
+    const int i = (int)(t % n);
+    t /= n;
+    const int be = (int)(t % ra1);
+    const int64_t b2 = t / ra1;
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) {
+      const double *w = W1 + a + (int64_t)r0 * ra0 * (j + (int64_t)n * b2);
+      const double *av = A + (int64_t)ra0 * (i + (int64_t)n * (j + (int64_t)n * be));
+      for (int al = 0; al < ra0; ++al) acc = fma(w[(int64_t)r0 * al], av[al], acc);
+    }
+    W2[e] = acc;
+  }
+}
+// stage 3: P'[b, c] = sum_l X[l, b] W[l, c] over l < L (the row pairs (a, i))
+__global__ void k_e_close(const double *X, const double *Wm, double *Pn, int L, int r1,
+                          int64_t ncol) {
+  const int64_t ne = (int64_t)r1 * ncol;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(e % r1);
+    const int64_t col = e / r1;
+    const double *xb = X + (int64_t)L * b, *wc = Wm + (int64_t)L * col;
+    double acc = 0.0;
+    for (int l = 0; l < L; ++l) acc = fma(xb[l], wc[l], acc);
+    Pn[e] = acc;
+  }
+}
+
+// right step of <x, A y>: P[a, al, a'] from P'[b, be, b']
+// stage 1: V1[a, i, c] = sum_b X[a, i, b] P'[b, c] over the column index c
+__global__ void k_e_open(const double *X, const double *Pn, double *V1, int r0n, int r1,
+                         int64_t ncol) {
+  const int64_t ne = (int64_t)r0n * ncol;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ai = e % r0n, c = e / r0n;
+    double acc = 0.0;
+    for (int b = 0; b < r1; ++b) acc = fma(X[ai + (int64_t)r0n * b], Pn[b + (int64_t)r1 * c], acc);
+    V1[e] = acc;
+  }
+}
+// stage 2: V2[a, al, j, b'] = sum_{be, i} V1[a, i, be, b'] A[al, i, j, be]
+__global__ void k_e3r_2(const double *V1, const double *A, double *V2, int r0, int ra0, int n,
+                        int ra1, int r1) {
+  const int64_t ne = (int64_t)r0 * ra0 * n * r1;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e % r0);
+    int64_t t = e / r0;
+    const int al = (int)(t % ra0);
+    t /= ra0;
+    const int j = (int)(t % n);
+    const int64_t b2 = t / n;
+    double acc = 0.0;
+    for (int be = 0; be < ra1; ++be)
+      for (int i = 0; i < n; ++i)
+        acc = fma(V1[a + (int64_t)r0 * (i + (int64_t)n * (be + (int64_t)ra1 * b2))],
+                  A[al + (int64_t)ra0 * (i + (int64_t)n * (j + (int64_t)n * be))], acc);
+    V2[e] = acc;
+  }
+}
+// stage 3: P[a, al, a'] = sum_{j, b'} V2[a, al, j, b'] Y[a', j, b']
+__global__ void k_e3r_3(const double *V2, const double *Y, double *P, int r0, int ra0, int n,
+                        int r1) {
+  const int64_t ra = (int64_t)r0 * ra0, ne = ra * r0;
+  const int nb = n * r1;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t aal = e % ra;
+    const int a2 = (int)(e / ra);
+    double acc = 0.0;
+    for (int jb = 0; jb < nb; ++jb) acc = fma(V2[aal + ra * jb], Y[a2 + (int64_t)r0 * jb], acc);
+    P[e] = acc;
+  }
+}
+
+// left step of <x, f>, stage 1: T[a, i, d] = sum_c Q[a, c] F[c, i, d]
+__global__ void k_e2l_1(const double *Q, const double *F, double *Tm, int r0, int rf0, int n,
+                        int rf1) {
+  const int64_t ne = (int64_t)r0 * n * rf1;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e % r0);
+    const int64_t id = e / r0;
+    double acc = 0.0;
+    for (int c = 0; c < rf0; ++c) acc = fma(Q[a + (int64_t)r0 * c], F[c + (int64_t)rf0 * id], acc);
+    Tm[e] = acc;
+  }
+}
+// right step of <x, f>, stage 2: Q[a, c] = sum_{i, d} T[a, i, d] F[c, i, d]
+__global__ void k_e2r_2(const double *Tm, const double *F, double *Q, int r0, int rf0, int n,
+                        int rf1) {
+  const int64_t ne = (int64_t)r0 * rf0;
+  const int nd = n * rf1;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e % r0), c = (int)(e / r0);
+    double acc = 0.0;
+    for (int id = 0; id < nd; ++id)
+      acc = fma(Tm[a + (int64_t)r0 * id], F[c + (int64_t)rf0 * id], acc);
+    Q[e] = acc;
+  }
+}
+
+// ---------------------------------------------------------------- local system
+// T[a, a', i, j, be] = sum_al L[a, al, a'] K[al, i, j, be]
+__global__ void k_local_T(const double *L, const double *K, double *T, int r0, int ra0, int n,
+                          int ra1) {
+  const int64_t ne = (int64_t)r0 * r0 * n * n * ra1;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int aa = (int)(e % ((int64_t)r0 * r0));  // a + r0 a'
+    const int64_t ijb = e / ((int64_t)r0 * r0);    // i + n (j + n be)
+    const int a = aa % r0, a2 = aa / r0;
+    double acc = 0.0;
+    for (int al = 0; al < ra0; ++al)
+      acc = fma(L[a + (int64_t)r0 * (al + (int64_t)ra0 * a2)], K[al + (int64_t)ra0 * ijb], acc);
+    T[e] = acc;
+  }
+}
+
+// B[p, q] = sum_be T[a, a', i, j, be] R[b, be, b'], p = a + r0 (i + n b),
+// q = a' + r0 (j + n b'); N = r0 n r1
+__global__ void k_local_B(const double *T, const double *R, double *B, int r0, int n, int ra1,
+                          int r1) {
+  const int64_t N = (int64_t)r0 * n * r1;
+  const int64_t ne = N * N;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e % N, q = e / N;
+    const int a = (int)(p % r0);
+    const int i = (int)((p / r0) % n);
+    const int b = (int)(p / ((int64_t)r0 * n));
+    const int a2 = (int)(q % r0);
+    const int j = (int)((q / r0) % n);
+    const int b2 = (int)(q / ((int64_t)r0 * n));
+    const double *t = T + (a + (int64_t)r0 * a2) + (int64_t)r0 * r0 * (i + (int64_t)n * j);
+    const int64_t tstride = (int64_t)r0 * r0 * n * n;
+    double acc = 0.0;
+    for (int be = 0; be < ra1; ++be)
+      acc = fma(t[tstride * be], R[b + (int64_t)r1 * (be + (int64_t)ra1 * b2)], acc);
+    B[e] = acc;
+  }
+}
+
+// g[a, i, b] = sum_{c, d} Lf[a, c] F[c, i, d] Rf[b, d]
+__global__ void k_local_g(const double *Lf, const double *F, const double *Rf, double *g, int r0,
+                          int rf0, int n, int r1, int rf1) {
+  const int64_t N = (int64_t)r0 * n * r1;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e % r0);
+    const int i = (int)((e / r0) % n);
+    const int b = (int)(e / ((int64_t)r0 * n));
+    double acc = 0.0;
+    for (int d = 0; d < rf1; ++d) {
+      double s = 0.0;
+      for (int c = 0; c < rf0; ++c)
+        s = fma(Lf[a + (int64_t)r0 * c], F[c + (int64_t)rf0 * (i + (int64_t)n * d)], s);
+      acc = fma(s, Rf[b + (int64_t)r1 * d], acc);
+    }
+    g[e] = acc;
+  }
+}
+
+// ---------------------------------------------------------------- Cholesky
+// factor the diagonal block A[k0:k0+kb, k0:k0+kb] (lower) in LDS; flag[0]
+// is set when a pivot is not positive
+__global__ void __launch_bounds__(AWG) k_potrf_diag(double *A, int64_t N, int k0, int kb,
+                                                    int *flag) {
+  __shared__ double S[CB][CB + 1];
+  for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
+    const int i = e % kb, j = e / kb;
+    S[i][j] = A[(k0 + i) + N * (k0 + j)];
+  }
+  __syncthreads();
+  for (int j = 0; j < kb; ++j) {
+    const double d = S[j][j];
+    __syncthreads();
+    if (!(d > 0.0)) {
+      if (threadIdx.x == 0) flag[0] = 1;
+      return;
+    }
+    const double s = sqrt(d);
+    for (int i = j + threadIdx.x; i < kb; i += blockDim.x) S[i][j] = (i == j) ? s : S[i][j] / s;
+    __syncthreads();
+    // trailing update of the block: S[i][l] -= S[i][j] S[l][j], j < l <= i
+    for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
+      const int i = e % kb, l = e / kb;
+      if (l > j && i >= l) S[i][l] -= S[i][j] * S[l][j];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
+    const int i = e % kb, j = e / kb;
+    if (i >= j) A[(k0 + i) + N * (k0 + j)] = S[i][j];
+  }
+}
+
+// rows k0+CB .. N-1 of a full panel: A21 <- A21 L11^-T (forward
+// substitution along each row, the row held in registers, L11 in LDS).
+// Only full panels have rows below them, so the width is the constant CB.
+__global__ void __launch_bounds__(AWG) k_trsm_panel(double *A, int64_t N, int k0) {
+  __shared__ double Lt[CB][CB + 1];
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+    const int i = e % CB, j = e / CB;
+    Lt[i][j] = (i >= j) ? A[(k0 + i) + N * (k0 + j)] : 0.0;
+  }
+  __syncthreads();
+  const int64_t row = (int64_t)k0 + CB + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (row >= N) return;
+  double x[CB];
+#pragma unroll
+  for (int j = 0; j < CB; ++j) x[j] = A[row + N * (k0 + j)];
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    double v = x[j];
+#pragma unroll
+    for (int l = 0; l < j; ++l) v -= x[l] * Lt[j][l];
+    x[j] = v / Lt[j][j];
+  }
+#pragma unroll
+  for (int j = 0; j < CB; ++j) A[row + N * (k0 + j)] = x[j];
+}
+
+// trailing update A22 -= L21 L21^T on the lower triangle, 64 x 64 tiles
+__global__ void __launch_bounds__(256) k_syrk_update(double *A, int64_t N, int k0, int kb) {
+  const int64_t s0 = (int64_t)k0 + kb;
+  const int64_t m0 = s0 + (int64_t)blockIdx.x * 64, n0 = s0 + (int64_t)blockIdx.y * 64;
+  if (n0 > m0 + 63 || m0 >= N || n0 >= N) return;  // tile entirely above the diagonal
+  __shared__ double As[CB][65], Bs[CB][65];
+  for (int e = threadIdx.x; e < 64 * kb; e += 256) {
+    const int r = e % 64, c = e / 64;
+    As[c][r] = (m0 + r < N) ? A[(m0 + r) + N * (k0 + c)] : 0.0;
+    Bs[c][r] = (n0 + r < N) ? A[(n0 + r) + N * (k0 + c)] : 0.0;
+  }
+  __syncthreads();
+  const int tr = threadIdx.x % 16, tc = threadIdx.x / 16;
+  double acc[4][4] = {};
+  for (int c = 0; c < kb; ++c) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = As[c][tr + 16 * u];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) b[v] = Bs[c][tc + 16 * v];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t gm = m0 + tr + 16 * u, gn = n0 + tc + 16 * v;
+      if (gm < N && gn < N && gm >= gn) A[gm + N * gn] -= acc[u][v];
+    }
+}
+
+// forward / backward substitution with the factor, block by block: the
+// diagonal block (staged in LDS, one wavefront, column-oriented
+// elimination), then the update of the remaining rows
+__global__ void __launch_bounds__(64) k_trsv_diag(const double *A, int64_t N, int k0, int kb,
+                                                  double *z, int lower) {
+  __shared__ double Ls[CB][CB + 1];
+  __shared__ double zs[CB];
+  for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
+    const int i = e % kb, j = e / kb;
+    Ls[i][j] = (i >= j) ? A[(k0 + i) + N * (k0 + j)] : 0.0;
+  }
+  const int t = threadIdx.x;
+  if (t < kb) zs[t] = z[k0 + t];
+  __syncthreads();
+  if (lower) {
+    for (int j = 0; j < kb; ++j) {
+      const double zj = zs[j] / Ls[j][j];
+      __syncthreads();
+      if (t == j) zs[j] = zj;
+      if (t > j && t < kb) zs[t] -= Ls[t][j] * zj;
+      __syncthreads();
+    }
+  } else {
+    for (int j = kb - 1; j >= 0; --j) {
+      const double zj = zs[j] / Ls[j][j];
+      __syncthreads();
+      if (t == j) zs[j] = zj;
+      if (t < j) zs[t] -= Ls[j][t] * zj;
+      __syncthreads();
+    }
+  }
+  if (t < kb) z[k0 + t] = zs[t];
+}
+
+// lower: z[i] -= sum_{j in block} L[i, j] z[j] for i after the block;
+// upper (L^T): z[i] -= sum_{j in block} L[j, i] z[j] for i before the block
+__global__ void k_trsv_update(const double *A, int64_t N, int k0, int kb, double *z, int lower) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (lower) {
+    const int64_t row = k0 + kb + i;
+    if (row >= N) return;
+    double s = 0.0;
+    for (int j = 0; j < kb; ++j) s = fma(A[row + N * (k0 + j)], z[k0 + j], s);
+    z[row] -= s;
+  } else {
+    if (i >= k0) return;
+    double s = 0.0;
+    for (int j = 0; j < kb; ++j) s = fma(A[(k0 + j) + N * i], z[k0 + j], s);
+    z[i] -= s;
+  }
+}
+
+// ---------------------------------------------------------------- QR
+__device__ double blk_sum(double v, double *red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+  return t;
+}
+
+// Householder QR of W (rows x cols, ld rows, cols <= rows) in global memory
+// (one block): R -> Rout (cols x cols), Q (rows x cols) -> W
+__global__ void __launch_bounds__(AWG) k_qr_thin(double *W, int rows, int cols, double *Rout,
+                                                 double *tau) {
+  __shared__ double red[AWG / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int j = 0; j < cols; ++j) {
+    double *wj = W + (int64_t)rows * j;
+    double p = 0.0;
+    for (int i = j + 1 + threadIdx.x; i < rows; i += blockDim.x) p += wj[i] * wj[i];
+    const double xn2 = blk_sum(p, red);
+    const double alpha = wj[j];
+    double t = 0.0, beta = alpha, scale = 0.0;
+    if (xn2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      t = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    __syncthreads();
+    if (t != 0.0)
+      for (int i = j + 1 + threadIdx.x; i < rows; i += blockDim.x) wj[i] *= scale;
+    if (threadIdx.x == 0) {
+      wj[j] = beta;
+      tau[j] = t;
+    }
+    __syncthreads();
+    if (t != 0.0) {
+      for (int c = j + 1 + wave; c < cols; c += nw) {
+        double *wc = W + (int64_t)rows * c;
+        double s = (lane == 0) ? wc[j] : 0.0;
+        for (int i = j + 1 + lane; i < rows; i += 64) s += wj[i] * wc[i];
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        s *= t;
+        if (lane == 0) wc[j] -= s;
+        for (int i = j + 1 + lane; i < rows; i += 64) wc[i] -= s * wj[i];
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < cols * cols; e += blockDim.x) {
+    const int i = e % cols, c = e / cols;
+    Rout[e] = (i <= c) ? W[i + (int64_t)rows * c] : 0.0;
+  }
+  __syncthreads();
+  // form Q in place: apply the reflectors to the identity columns, last first;
+  // the reflector of column j is kept in a register copy before overwriting
+  for (int j = cols - 1; j >= 0; --j) {
+    const double t = tau[j];
+    double *wj = W + (int64_t)rows * j;
+    // columns c > j already hold Q's columns; apply H_j to them
+    if (t != 0.0) {
+      for (int c = j + 1 + wave; c < cols; c += nw) {
+        double *qc = W + (int64_t)rows * c;
+        double s = 0.0;
+        for (int i = j + 1 + lane; i < rows; i += 64) s += wj[i] * qc[i];
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        s *= t;  // qc[j] is 0 before this reflector
+        if (lane == 0) qc[j] = -s;
+        for (int i = j + 1 + lane; i < rows; i += 64) qc[i] -= s * wj[i];
+      }
+    }
+    __syncthreads();
+    // column j of Q: H_j e_j = e_j - t v (v_j = 1)
+    for (int i = threadIdx.x; i < rows; i += blockDim.x) {
+      const double vi = (i < j) ? 0.0 : (i == j ? 1.0 : wj[i]);
+      wj[i] = (i == j ? 1.0 : 0.0) - t * vi;
+    }
+    __syncthreads();
+  }
+}
+
+// C (M x N) = A (M x K) B (K x N), or with B transposed; small, column-major
+__global__ void k_gemm_small(const double *A, int lda, const double *B, int ldb, int tb, double *C,
+                             int ldc, int M, int N, int K) {
+  const int64_t ne = (int64_t)M * N;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int m = (int)(e % M), nn = (int)(e / M);
+    double acc = 0.0;
+    for (int k = 0; k < K; ++k)
+      acc = fma(A[m + (int64_t)lda * k], tb ? B[nn + (int64_t)ldb * k] : B[k + (int64_t)ldb * nn],
+                acc);
+    C[m + (int64_t)ldc * nn] = acc;
+  }
+}
+
+// deterministic start values (integer hash, uniform in [-1, 1)), scaled
+__global__ void k_hash_fill(double *x, int64_t n, uint64_t seed, double scale) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(e + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[e] = scale * ((double)(z >> 11) * (1.0 / 4503599627370496.0) - 1.0);
+  }
+}
+
+// out[0] = sum_i a[i] b[i] (one workgroup)
+__global__ void __launch_bounds__(AWG) k_vdot(const double *a, const double *b, int64_t n,
+                                              double *out) {
+  __shared__ double red[AWG / 64];
+  double p = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p = fma(a[i], b[i], p);
+  const double t = blk_sum(p, red);
+  if (threadIdx.x == 0) out[0] = t;
+}
+
+// dst (cols x rows) = src (rows x cols)^T, column-major
+__global__ void k_transpose(const double *src, int rows, int cols, double *dst) {
+  const int64_t ne = (int64_t)rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % rows), c = (int)(e / rows);
+    dst[c + (int64_t)cols * r] = src[e];
+  }
+}
+
+__global__ void k_fill_value(double *x, int64_t n, double v) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    x[e] = v;
+}
+
+// dst (r0d x n x r1d) = src (r0s x n x r1s) zero-padded
+__global__ void k_pad_core(const double *src, int r0s, int n, int r1s, double *dst, int r0d,
+                           int r1d) {
+  const int64_t ne = (int64_t)r0d * n * r1d;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e % r0d);
+    const int i = (int)((e / r0d) % n);
+    const int b = (int)(e / ((int64_t)r0d * n));
+    dst[e] = (a < r0s && b < r1s) ? src[a + (int64_t)r0s * (i + (int64_t)n * b)] : 0.0;
+  }
+}
+
+int blocks_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+hipError_t als_env3_left(const double *P, const double *X, const double *A, const double *Y,
+                         double *Pn, double *W1, double *W2, int r0, int ra0, int n, int ra1,
+                         int r1, hipStream_t s) {
+  const int64_t n1 = (int64_t)r0 * ra0 * n * r1, n2 = (int64_t)r0 * n * ra1 * r1;
+  hipLaunchKernelGGL(k_e3l_1, dim3(blocks_for(n1)), dim3(256), 0, s, P, Y, W1, r0, ra0, n, r1);
+  hipLaunchKernelGGL(k_e3l_2, dim3(blocks_for(n2)), dim3(256), 0, s, W1, A, W2, r0, ra0, n, ra1,
+                     r1);
+  const int64_t nc = (int64_t)ra1 * r1;
+  hipLaunchKernelGGL(k_e_close, dim3(blocks_for(r1 * nc)), dim3(256), 0, s, X, W2, Pn, r0 * n, r1,
+                     nc);
+  return hipGetLastError();
+}
+hipError_t als_env3_right(const double *Pn, const double *X, const double *A, const double *Y,
+                          double *P, double *W1, double *W2, int r0, int ra0, int n, int ra1,
+                          int r1, hipStream_t s) {
+  const int64_t nc = (int64_t)ra1 * r1;
+  hipLaunchKernelGGL(k_e_open, dim3(blocks_for((int64_t)r0 * n * nc)), dim3(256), 0, s, X, Pn, W1,
+                     r0 * n, r1, nc);
+  const int64_t n2 = (int64_t)r0 * ra0 * n * r1;
+  hipLaunchKernelGGL(k_e3r_2, dim3(blocks_for(n2)), dim3(256), 0, s, W1, A, W2, r0, ra0, n, ra1,
+                     r1);
+  hipLaunchKernelGGL(k_e3r_3, dim3(blocks_for((int64_t)r0 * ra0 * r0)), dim3(256), 0, s, W2, Y, P,
+                     r0, ra0, n, r1);
+  return hipGetLastError();
+}
+hipError_t als_env2_left(const double *Q, const double *X, const double *F, double *Qn,
+                         double *Tm, int r0, int rf0, int n, int r1, int rf1, hipStream_t s) {
+  hipLaunchKernelGGL(k_e2l_1, dim3(blocks_for((int64_t)r0 * n * rf1)), dim3(256), 0, s, Q, F, Tm,
+                     r0, rf0, n, rf1);
+  hipLaunchKernelGGL(k_e_close, dim3(blocks_for((int64_t)r1 * rf1)), dim3(256), 0, s, X, Tm, Qn,
+                     r0 * n, r1, (int64_t)rf1);
+  return hipGetLastError();
+}
+hipError_t als_env2_right(const double *Qn, const double *X, const double *F, double *Q,
+                          double *Tm, int r0, int rf0, int n, int r1, int rf1, hipStream_t s) {
+  hipLaunchKernelGGL(k_e_open, dim3(blocks_for((int64_t)r0 * n * rf1)), dim3(256), 0, s, X, Qn, Tm,
+                     r0 * n, r1, (int64_t)rf1);
+  hipLaunchKernelGGL(k_e2r_2, dim3(blocks_for((int64_t)r0 * rf0)), dim3(256), 0, s, Tm, F, Q, r0,
+                     rf0, n, rf1);
+  return hipGetLastError();
+}
+
+hipError_t als_local_system(const double *L, const double *K, const double *R, const double *Lf,
+                            const double *F, const double *Rf, double *T, double *B, double *g,
+                            int r0, int ra0, int n, int ra1, int r1, int rf0, int rf1,
+                            hipStream_t s) {
+  const int64_t nt = (int64_t)r0 * r0 * n * n * ra1;
+  hipLaunchKernelGGL(k_local_T, dim3(blocks_for(nt)), dim3(256), 0, s, L, K, T, r0, ra0, n, ra1);
+  const int64_t N = (int64_t)r0 * n * r1;
+  hipLaunchKernelGGL(k_local_B, dim3(blocks_for(N * N)), dim3(256), 0, s, T, R, B, r0, n, ra1, r1);
+  hipLaunchKernelGGL(k_local_g, dim3(blocks_for(N)), dim3(256), 0, s, Lf, F, Rf, g, r0, rf0, n, r1,
+                     rf1);
+  return hipGetLastError();
+}
+
+// B (N x N, SPD) y = g, overwriting B by its Cholesky factor and g by y
+hipError_t als_cholesky_solve(double *B, int64_t N, double *g, int *flag, hipStream_t s) {
+  for (int64_t k0 = 0; k0 < N; k0 += CB) {
+    const int kb = (int)std::min<int64_t>(CB, N - k0);
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(AWG), 0, s, B, N, (int)k0, kb, flag);
+    const int64_t rest = N - k0 - kb;
+    if (rest > 0) {
+      // rest > 0 implies a full panel (kb == CB)
+      hipLaunchKernelGGL(k_trsm_panel, dim3((int)((rest + AWG - 1) / AWG)), dim3(AWG), 0, s, B, N,
+                         (int)k0);
+      const int t = (int)((rest + 63) / 64);
+      hipLaunchKernelGGL(k_syrk_update, dim3(t, t), dim3(256), 0, s, B, N, (int)k0, kb);
+    }
+  }
+  for (int64_t k0 = 0; k0 < N; k0 += CB) {
+    const int kb = (int)std::min<int64_t>(CB, N - k0);
+    hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(64), 0, s, B, N, (int)k0, kb, g, 1);
+    const int64_t rest = N - k0 - kb;
+    if (rest > 0)
+      hipLaunchKernelGGL(k_trsv_update, dim3(blocks_for(rest)), dim3(256), 0, s, B, N, (int)k0, kb,
+                         g, 1);
+  }
+  const int64_t nb = (N + CB - 1) / CB;
+  for (int64_t b = nb - 1; b >= 0; --b) {
+    const int64_t k0 = b * CB;
+    const int kb = (int)std::min<int64_t>(CB, N - k0);
+    hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(64), 0, s, B, N, (int)k0, kb, g, 0);
+    if (k0 > 0)
+      hipLaunchKernelGGL(k_trsv_update, dim3(blocks_for(k0)), dim3(256), 0, s, B, N, (int)k0, kb,
+                         g, 0);
+  }
+  return hipGetLastError();
+}
+
+hipError_t als_qr(double *W, int rows, int cols, double *R, double *tau, hipStream_t s) {
+  hipLaunchKernelGGL(k_qr_thin, dim3(1), dim3(AWG), 0, s, W, rows, cols, R, tau);
+  return hipGetLastError();
+}
+
+hipError_t als_gemm(const double *A, int lda, const double *B, int ldb, bool tb, double *C, int ldc,
+                    int M, int N, int K, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemm_small, dim3(blocks_for((int64_t)M * N)), dim3(256), 0, s, A, lda, B,
+                     ldb, tb ? 1 : 0, C, ldc, M, N, K);
+  return hipGetLastError();
+}
+
+hipError_t als_fill(double *x, int64_t n, uint64_t seed, double scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_hash_fill, dim3(blocks_for(n)), dim3(256), 0, s, x, n, seed, scale);
+  return hipGetLastError();
+}
+
+hipError_t als_vdot(const double *a, const double *b, int64_t n, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_vdot, dim3(1), dim3(AWG), 0, s, a, b, n, out);
+  return hipGetLastError();
+}
+
+hipError_t als_transpose(const double *src, int rows, int cols, double *dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose, dim3(blocks_for((int64_t)rows * cols)), dim3(256), 0, s, src,
+                     rows, cols, dst);
+  return hipGetLastError();
+}
+
+hipError_t als_fill_value(double *x, int64_t n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_value, dim3(blocks_for(n)), dim3(256), 0, s, x, n, v);
+  return hipGetLastError();
+}
+
+hipError_t als_pad_core(const double *src, int r0s, int n, int r1s, double *dst, int r0d, int r1d,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_pad_core, dim3(blocks_for((int64_t)r0d * n * r1d)), dim3(256), 0, s, src,
+                     r0s, n, r1s, dst, r0d, r1d);
+  return hipGetLastError();
+}
+
+}  // namespace qtt
