@@ -46,7 +46,7 @@ def _parse():
                     help="only launch the level-10 product 5 times and a plain 423 MB device "
                          "copy 5 times (for hardware counter passes), print their sizes, exit")
     ap.add_argument("--no-solve", dest="solve", action="store_false",
-                    help="skip the level-5 solve measurement")
+                    help="skip the level-5 and level-10 solve measurements")
     ap.add_argument("--batch", type=int, default=64,
                     help="cases of the batched-step measurement (0: skip)")
     return ap.parse_args()
@@ -250,6 +250,31 @@ def cpu_baseline(level, nbytes, seconds):
                        % (D, t_mv, done, t_rd, D, per_step))
 
 
+def level10_solve(P, torch, level: int):
+    """The level-10 configuration of the plain method: the traction workload
+    of the step, eps 1e-8, rank cap 64, solved by one-site ALS sweeps (FP64
+    local Cholesky solves) until the energy decrease over a sweep falls to
+    1e-12 relative (tol 1e-6 on its square root); solves/s of one solve after
+    a warm-up solve, the FP64 dense residual and the final rank."""
+    import workloads as W
+    prob = W.cantilever_traction(level)
+    K, f = P.assemble(prob)
+    opts = P.SolveOpts(tol=1e-6, eps=EPS, rmax=RANK, maxit_out=12, method="als", seed=1)
+    ws = P._lib._workspace(P.solve_workspace_bytes(K, f, opts))
+    P.solve(K, f, opts, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, rep = P.solve(K, f, opts, ws=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dict(workload="unit square level %d (%d dofs), seeded 8-mode traction, eps %.0e, "
+                "rank cap %d, one-site ALS" % (level, 2 * 4 ** level, EPS, RANK),
+                solves_per_s=round(1.0 / dt, 4), ms_per_solve=round(1e3 * dt, 1),
+                sweeps=rep["outer"], local_solves=rep["inner"], status=rep["status"],
+                energy_decrease=float("%.3e" % rep["criterion"]),
+                fp64_residual=float("%.3e" % rep["residual"]), solution_max_rank=rep["max_rank"])
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -297,6 +322,7 @@ def main():
     mixed = mixed_precision(P, torch, K, x, ws, max(2, args.steps // 2))
     batched = batched_steps(P, torch, args.batch) if args.batch > 0 else None
     solve5 = small_solve(P, torch, 5) if args.solve else None
+    solve10 = level10_solve(P, torch, args.level) if args.solve else None
     line = {
         "metric": "QTT solves/sec and matvec+round GB/s at rel. err 1e-6 vs FP64 plain GPU",
         "value": round(value, 3),
@@ -316,7 +342,8 @@ def main():
                                % (args.level, 2 * 4 ** args.level, K.D, max(K.ranks), RANK,
                                   EPS, RANK, ELL),
                    "bytes_per_step": nbytes, "result_ranks_max": max(y.ranks),
-                   "mixed_precision": mixed, "batched_steps": batched, "solve_level5": solve5},
+                   "mixed_precision": mixed, "batched_steps": batched, "solve_level5": solve5,
+                   "solve_level%d" % args.level: solve10},
         "roofline": roof,
     }
     if not args.no_cpu:

@@ -236,12 +236,8 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
                                     RF[k + 1], s);
     if (e != hipSuccess) return e;
     const int64_t N = csize(k);
-    if ((e = hipMemcpyAsync(core(k), L.g, sizeof(double) * N, hipMemcpyDeviceToDevice, s)) !=
-        hipSuccess)
-      return e;
-    if ((e = als_cholesky_solve(L.B, N, core(k), L.flag, s)) != hipSuccess) return e;
     ++solves;
-    return als_vdot(core(k), L.g, N, L.sc + A_YG, s);
+    return als_cholesky_solve(L.B, N, L.g, core(k), L.flag, L.sc + A_YG, s);
   };
 
   // right-orthogonalise cores D-1..1, then the environments from the right

@@ -219,48 +219,71 @@ __global__ void k_local_g(const double *Lf, const double *F, const double *Rf, d
 }
 
 // ---------------------------------------------------------------- Cholesky
-// factor the diagonal block A[k0:k0+kb, k0:k0+kb] (lower) in LDS; flag[0]
-// is set when a pivot is not positive
-__global__ void __launch_bounds__(AWG) k_potrf_diag(double *A, int64_t N, int k0, int kb,
-                                                    int *flag) {
-  __shared__ double S[CB][CB + 1];
-  for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
-    const int i = e % kb, j = e / kb;
-    S[i][j] = A[(k0 + i) + N * (k0 + j)];
-  }
-  __syncthreads();
-  for (int j = 0; j < kb; ++j) {
-    const double d = S[j][j];
+// Blocked right-looking Cholesky B = L L^T with the forward substitution
+// L z = g folded into the panel kernels, then a blocked backward
+// substitution L^T y = z.  Panels are CB = 64 columns wide; the trailing
+// update is deferred over strips of NB = 256 columns (inner updates touch
+// only the strip), so the trailing matrix is read and written once per strip
+// by an FP64 MFMA kernel.
+constexpr int NB = 256;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// factor the diagonal block A[k0:k0+kb, k0:k0+kb] (one wavefront, lane i
+// holds row i in registers; the active column is broadcast through LDS),
+// then z1 = L11^-1 g1 in place in g.  Lanes >= kb carry an identity row.
+// *flag becomes 1 when a pivot is not positive.
+__global__ void __launch_bounds__(64) k_potrf_fwd(double *A, int64_t N, int k0, int kb, double *g,
+                                                  int *flag) {
+  __shared__ double col[CB];
+  const int i = threadIdx.x;
+  const bool live = i < kb;
+  double x[CB];
+#pragma unroll
+  for (int j = 0; j < CB; ++j)
+    x[j] = (live && j <= i) ? A[(k0 + i) + N * (k0 + j)] : (i == j ? 1.0 : 0.0);
+  double gi = live ? g[k0 + i] : 0.0;
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    const double piv = __shfl(x[j], j, 64);
+    bad = bad || !(piv > 0.0);
+    const double sq = sqrt(piv > 0.0 ? piv : 1.0);
+    x[j] = (i == j) ? sq : (i > j ? x[j] / sq : 0.0);
+    col[i] = x[j];
     __syncthreads();
-    if (!(d > 0.0)) {
-      if (threadIdx.x == 0) flag[0] = 1;
-      return;
-    }
-    const double s = sqrt(d);
-    for (int i = j + threadIdx.x; i < kb; i += blockDim.x) S[i][j] = (i == j) ? s : S[i][j] / s;
-    __syncthreads();
-    // trailing update of the block: S[i][l] -= S[i][j] S[l][j], j < l <= i
-    for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
-      const int i = e % kb, l = e / kb;
-      if (l > j && i >= l) S[i][l] -= S[i][j] * S[l][j];
-    }
+#pragma unroll
+    for (int l = j + 1; l < CB; ++l)
+      if (i >= l) x[l] = fma(-x[j], col[l], x[l]);
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
-    const int i = e % kb, j = e / kb;
-    if (i >= j) A[(k0 + i) + N * (k0 + j)] = S[i][j];
+  // forward substitution on the block: lane j finishes z_j, the lanes below
+  // subtract its contribution
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    const double zj = __shfl(gi / x[j], j, 64);
+    if (i == j) gi = zj;
+    else if (i > j) gi = fma(-x[j], zj, gi);
   }
+  if (live) {
+#pragma unroll
+    for (int j = 0; j < CB; ++j)
+      if (j <= i) A[(k0 + i) + N * (k0 + j)] = x[j];
+    g[k0 + i] = gi;
+  }
+  if (bad && i == 0) flag[0] = 1;
 }
 
-// rows k0+CB .. N-1 of a full panel: A21 <- A21 L11^-T (forward
-// substitution along each row, the row held in registers, L11 in LDS).
-// Only full panels have rows below them, so the width is the constant CB.
-__global__ void __launch_bounds__(AWG) k_trsm_panel(double *A, int64_t N, int k0) {
+// rows k0+CB .. N-1 of a full panel: A21 <- A21 L11^-T (each row held in
+// registers, L11 in LDS), then g2 <- g2 - A21 z1.  Only full panels have
+// rows below them, so the width is the constant CB.
+__global__ void __launch_bounds__(64) k_trsm_fwd(double *A, int64_t N, int k0, double *g) {
   __shared__ double Lt[CB][CB + 1];
+  __shared__ double zs[CB];
   for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
     const int i = e % CB, j = e / CB;
     Lt[i][j] = (i >= j) ? A[(k0 + i) + N * (k0 + j)] : 0.0;
   }
+  zs[threadIdx.x] = g[k0 + threadIdx.x];
   __syncthreads();
   const int64_t row = (int64_t)k0 + CB + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (row >= N) return;
@@ -271,96 +294,108 @@ __global__ void __launch_bounds__(AWG) k_trsm_panel(double *A, int64_t N, int k0
   for (int j = 0; j < CB; ++j) {
     double v = x[j];
 #pragma unroll
-    for (int l = 0; l < j; ++l) v -= x[l] * Lt[j][l];
+    for (int l = 0; l < j; ++l) v = fma(-x[l], Lt[j][l], v);
     x[j] = v / Lt[j][j];
   }
+  double sg = 0.0;
 #pragma unroll
-  for (int j = 0; j < CB; ++j) A[row + N * (k0 + j)] = x[j];
+  for (int j = 0; j < CB; ++j) {
+    A[row + N * (k0 + j)] = x[j];
+    sg = fma(x[j], zs[j], sg);
+  }
+  g[row] -= sg;
 }
 
-// trailing update A22 -= L21 L21^T on the lower triangle, 64 x 64 tiles
-__global__ void __launch_bounds__(256) k_syrk_update(double *A, int64_t N, int k0, int kb) {
-  const int64_t s0 = (int64_t)k0 + kb;
-  const int64_t m0 = s0 + (int64_t)blockIdx.x * 64, n0 = s0 + (int64_t)blockIdx.y * 64;
-  if (n0 > m0 + 63 || m0 >= N || n0 >= N) return;  // tile entirely above the diagonal
-  __shared__ double As[CB][65], Bs[CB][65];
-  for (int e = threadIdx.x; e < 64 * kb; e += 256) {
-    const int r = e % 64, c = e / 64;
-    As[c][r] = (m0 + r < N) ? A[(m0 + r) + N * (k0 + c)] : 0.0;
-    Bs[c][r] = (n0 + r < N) ? A[(n0 + r) + N * (k0 + c)] : 0.0;
-  }
-  __syncthreads();
-  const int tr = threadIdx.x % 16, tc = threadIdx.x / 16;
-  double acc[4][4] = {};
-  for (int c = 0; c < kb; ++c) {
-    double a[4], b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] = As[c][tr + 16 * u];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) b[v] = Bs[c][tc + 16 * v];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t gm = m0 + tr + 16 * u, gn = n0 + tc + 16 * v;
-      if (gm < N && gn < N && gm >= gn) A[gm + N * gn] -= acc[u][v];
+// A[m, n] -= sum_{c in [kc0, kc0+kd)} A[m, c] A[n, c] for nb <= n < ne,
+// n <= m < N (lower triangle), 64 x 64 output tiles per workgroup; each
+// wavefront owns a 32 x 32 quarter as 2 x 2 blocks of
+// v_mfma_f64_16x16x4f64 (A operand: lane l holds row l%16, depth l/16; B
+// likewise for the column; result: element v of lane l is row l/16 + 4v of
+// column l%16).  Depth is staged through LDS in chunks of KC.
+constexpr int KC = 32;
+__global__ void __launch_bounds__(256) k_syrk_mfma(double *A, int64_t N, int kc0, int kd, int nb,
+                                                   int ne) {
+  const int64_t m0 = nb + (int64_t)blockIdx.x * 64, n0 = nb + (int64_t)blockIdx.y * 64;
+  if (n0 > m0 + 63) return;  // tile strictly above the diagonal
+  __shared__ double As[64][KC + 1], Bs[64][KC + 1];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int rr = lane & 15, kq = lane >> 4;
+  dbl4 acc00 = {0.0, 0.0, 0.0, 0.0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
+  for (int c0 = 0; c0 < kd; c0 += KC) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * KC; e += 256) {
+      const int r = e % 64, c = e / 64;
+      const bool cv = c0 + c < kd;
+      const int64_t cc = N * (int64_t)(kc0 + c0 + c);
+      As[r][c] = (cv && m0 + r < N) ? A[(m0 + r) + cc] : 0.0;
+      Bs[r][c] = (cv && n0 + r < N) ? A[(n0 + r) + cc] : 0.0;
     }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const double a0 = As[wr + rr][kk + kq], a1 = As[wr + 16 + rr][kk + kq];
+      const double b0 = Bs[wc + rr][kk + kq], b1 = Bs[wc + 16 + rr][kk + kq];
+      acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
+      acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
+      acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
+      acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
+    }
+  }
+  const dbl4 accs[2][2] = {{acc00, acc01}, {acc10, acc11}};
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gm = m0 + wr + 16 * bi + kq + 4 * v, gn = n0 + wc + 16 * bj + rr;
+        if (gm < N && gn < ne && gm >= gn) A[gm + N * gn] -= accs[bi][bj][v];
+      }
 }
 
-// forward / backward substitution with the factor, block by block: the
-// diagonal block (staged in LDS, one wavefront, column-oriented
-// elimination), then the update of the remaining rows
-__global__ void __launch_bounds__(64) k_trsv_diag(const double *A, int64_t N, int k0, int kb,
-                                                  double *z, int lower) {
+// backward substitution step for the block [k0, k0+kb): every workgroup
+// solves L_bb^T y_b = z_b (one wavefront, shuffles), workgroup 0 stores y_b,
+// and each workgroup then updates its 128 entries of z below k0:
+// z_i -= sum_j L[k0+j, i] y_j (8 lanes per i reading the 64 contiguous
+// entries of column i's block row).
+constexpr int BWD_COLS = 128;
+__global__ void __launch_bounds__(256) k_bwd(const double *A, int64_t N, int k0, int kb,
+                                             double *z, double *y) {
   __shared__ double Ls[CB][CB + 1];
-  __shared__ double zs[CB];
+  __shared__ double ys[CB];
   for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
     const int i = e % kb, j = e / kb;
     Ls[i][j] = (i >= j) ? A[(k0 + i) + N * (k0 + j)] : 0.0;
   }
-  const int t = threadIdx.x;
-  if (t < kb) zs[t] = z[k0 + t];
   __syncthreads();
-  if (lower) {
-    for (int j = 0; j < kb; ++j) {
-      const double zj = zs[j] / Ls[j][j];
-      __syncthreads();
-      if (t == j) zs[j] = zj;
-      if (t > j && t < kb) zs[t] -= Ls[t][j] * zj;
-      __syncthreads();
-    }
-  } else {
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x;
+    double v = l < kb ? z[k0 + l] : 0.0;
     for (int j = kb - 1; j >= 0; --j) {
-      const double zj = zs[j] / Ls[j][j];
-      __syncthreads();
-      if (t == j) zs[j] = zj;
-      if (t < j) zs[t] -= Ls[j][t] * zj;
-      __syncthreads();
+      const double yj = __shfl(v, j, 64) / Ls[j][j];
+      if (l == j) v = yj;
+      else if (l < j) v = fma(-Ls[j][l], yj, v);
+    }
+    if (l < kb) {
+      ys[l] = v;
+      if (blockIdx.x == 0) y[k0 + l] = v;
     }
   }
-  if (t < kb) z[k0 + t] = zs[t];
-}
-
-// lower: z[i] -= sum_{j in block} L[i, j] z[j] for i after the block;
-// upper (L^T): z[i] -= sum_{j in block} L[j, i] z[j] for i before the block
-__global__ void k_trsv_update(const double *A, int64_t N, int k0, int kb, double *z, int lower) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (lower) {
-    const int64_t row = k0 + kb + i;
-    if (row >= N) return;
+  __syncthreads();
+  // 8 lanes per column: lane group q = lane / 8 owns column i, part p = lane % 8
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int q = lane >> 3, p = lane & 7;
+  const int64_t ibase = (int64_t)blockIdx.x * BWD_COLS;
+  for (int c = wave * 8 + q; c < BWD_COLS; c += 32) {
+    const int64_t i = ibase + c;
     double s = 0.0;
-    for (int j = 0; j < kb; ++j) s = fma(A[row + N * (k0 + j)], z[k0 + j], s);
-    z[row] -= s;
-  } else {
-    if (i >= k0) return;
-    double s = 0.0;
-    for (int j = 0; j < kb; ++j) s = fma(A[(k0 + j) + N * i], z[k0 + j], s);
-    z[i] -= s;
+    if (i < k0)
+      for (int j = p; j < kb; j += 8) s = fma(A[(k0 + j) + N * i], ys[j], s);
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    s += __shfl_xor(s, 4, 64);
+    if (i < k0 && p == 0) z[i] -= s;
   }
 }
 
@@ -573,36 +608,39 @@ hipError_t als_local_system(const double *L, const double *K, const double *R, c
   return hipGetLastError();
 }
 
-// B (N x N, SPD) y = g, overwriting B by its Cholesky factor and g by y
-hipError_t als_cholesky_solve(double *B, int64_t N, double *g, int *flag, hipStream_t s) {
-  for (int64_t k0 = 0; k0 < N; k0 += CB) {
-    const int kb = (int)std::min<int64_t>(CB, N - k0);
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(AWG), 0, s, B, N, (int)k0, kb, flag);
-    const int64_t rest = N - k0 - kb;
-    if (rest > 0) {
-      // rest > 0 implies a full panel (kb == CB)
-      hipLaunchKernelGGL(k_trsm_panel, dim3((int)((rest + AWG - 1) / AWG)), dim3(AWG), 0, s, B, N,
-                         (int)k0);
-      const int t = (int)((rest + 63) / 64);
-      hipLaunchKernelGGL(k_syrk_update, dim3(t, t), dim3(256), 0, s, B, N, (int)k0, kb);
+// B (N x N, SPD) y = g: B is overwritten by its Cholesky factor L and y
+// receives the solution; g is consumed.  zz (may be NULL) receives
+// <z, z> = <y, g> for z = L^-1 g.
+hipError_t als_cholesky_solve(double *B, int64_t N, double *g, double *y, int *flag, double *zz,
+                              hipStream_t s) {
+  for (int64_t K0 = 0; K0 < N; K0 += NB) {
+    const int64_t K1 = std::min<int64_t>(K0 + NB, N);
+    for (int64_t k0 = K0; k0 < K1; k0 += CB) {
+      const int kb = (int)std::min<int64_t>(CB, N - k0);
+      hipLaunchKernelGGL(k_potrf_fwd, dim3(1), dim3(64), 0, s, B, N, (int)k0, kb, g, flag);
+      const int64_t rest = N - k0 - kb;
+      if (rest > 0) {  // implies a full panel (kb == CB)
+        hipLaunchKernelGGL(k_trsm_fwd, dim3((int)((rest + 63) / 64)), dim3(64), 0, s, B, N,
+                           (int)k0, g);
+        const int64_t nb = k0 + CB;
+        if (nb < K1)
+          hipLaunchKernelGGL(k_syrk_mfma, dim3((int)((N - nb + 63) / 64), (int)((K1 - nb + 63) / 64)),
+                             dim3(256), 0, s, B, N, (int)k0, CB, (int)nb, (int)K1);
+      }
+    }
+    if (K1 < N) {
+      const int t = (int)((N - K1 + 63) / 64);
+      hipLaunchKernelGGL(k_syrk_mfma, dim3(t, t), dim3(256), 0, s, B, N, (int)K0, (int)(K1 - K0),
+                         (int)K1, (int)N);
     }
   }
-  for (int64_t k0 = 0; k0 < N; k0 += CB) {
-    const int kb = (int)std::min<int64_t>(CB, N - k0);
-    hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(64), 0, s, B, N, (int)k0, kb, g, 1);
-    const int64_t rest = N - k0 - kb;
-    if (rest > 0)
-      hipLaunchKernelGGL(k_trsv_update, dim3(blocks_for(rest)), dim3(256), 0, s, B, N, (int)k0, kb,
-                         g, 1);
-  }
-  const int64_t nb = (N + CB - 1) / CB;
-  for (int64_t b = nb - 1; b >= 0; --b) {
+  if (zz) hipLaunchKernelGGL(k_vdot, dim3(1), dim3(AWG), 0, s, g, g, N, zz);
+  const int64_t nblk = (N + CB - 1) / CB;
+  for (int64_t b = nblk - 1; b >= 0; --b) {
     const int64_t k0 = b * CB;
     const int kb = (int)std::min<int64_t>(CB, N - k0);
-    hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(64), 0, s, B, N, (int)k0, kb, g, 0);
-    if (k0 > 0)
-      hipLaunchKernelGGL(k_trsv_update, dim3(blocks_for(k0)), dim3(256), 0, s, B, N, (int)k0, kb,
-                         g, 0);
+    const int groups = (int)std::max<int64_t>(1, (k0 + BWD_COLS - 1) / BWD_COLS);
+    hipLaunchKernelGGL(k_bwd, dim3(groups), dim3(256), 0, s, B, N, (int)k0, kb, g, y);
   }
   return hipGetLastError();
 }
