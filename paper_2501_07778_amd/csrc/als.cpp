@@ -16,10 +16,12 @@
 //   * the active core moves by a QR (forward) or LQ (backward) step that
 //     passes the triangular factor into the next core, leaving u unchanged.
 // After a local solve J(u) = -<y, g_k>/2, so the energy is known after every
-// sweep without a global product; it can only decrease.  The sweeps stop when
-// the decrease over a sweep, relative to |J|, falls to tol^2 (J(u) - J(u*)
-// is half the squared energy-norm error, so the criterion bounds from below
-// the relative energy error of the iterate before that sweep).
+// sweep without a global product; it can only decrease (it is traced).  The
+// sweeps stop when the relative change of u over a sweep,
+// ||u_s - u_{s-1}|| / ||u_s||, falls to tol; the difference is formed as a
+// train (core concatenation) and its norm taken directly, so the criterion
+// resolves changes down to round-off (an energy difference would not: it is
+// quadratic in the change and cancels at FP64 precision near 1e-7).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -45,13 +47,16 @@ struct AlsLayout {
   double *sc = nullptr;           // device scalars
   int *flag = nullptr;            // Cholesky breakdown
   RoundWs rw;                     // final rounding at eps
+  TTDesc Up, Dif;                 // iterate of the previous sweep, u - u_prev
+  double *dot_ws = nullptr;
+  int64_t dot_elems = 0;
   TTDesc Ku, Rs;                  // residual check: K u and f - K u
   double *dense = nullptr, *full_ws = nullptr;
   int64_t N = 0;
   int32_t *rk_in = nullptr;       // device ranks of the packed K, f, x0
 };
 
-enum { A_YG = 0, A_FN2 = 2, A_RES = 4, A_COUNT = 8 };
+enum { A_YG = 0, A_FN2 = 2, A_RES = 4, A_DD = 6, A_UU = 7, A_COUNT = 8 };
 
 bool carve_als(Arena &ar, const qtt_tt *K, const qtt_tt *f, const qtt_solve_opts *o,
                AlsLayout &L) {
@@ -85,6 +90,12 @@ bool carve_als(Arena &ar, const qtt_tt *K, const qtt_tt *f, const qtt_solve_opts
   L.sc = (double *)ar.take(sizeof(double) * A_COUNT);
   L.flag = (int *)ar.take(sizeof(int) * 4);
   ok = round_ws_take(ar, L.U.v, L.rw) && ok;
+  ok = arena_tt(ar, L.Up, D, n, nullptr, c) && ok;
+  std::vector<int> dc(c);
+  for (int k = 1; k < D; ++k) dc[k] = 2 * c[k];
+  ok = arena_tt(ar, L.Dif, D, n, nullptr, dc) && ok;
+  L.dot_elems = std::max(dot_ws_elems(L.Dif.v, L.Dif.v), dot_ws_elems(L.U.v, L.U.v));
+  L.dot_ws = (double *)ar.take(sizeof(double) * L.dot_elems);
   // residual: K u has ranks R_k c_k, f - K u has f's ranks added
   std::vector<int> pc(c), rc(c);
   for (int k = 0; k <= D; ++k) {
@@ -188,6 +199,7 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
   {
     std::vector<int32_t> c32(c.begin(), c.end());
     QTT_HIP(upload_ranks(L.U.v, c32.data(), s));
+    QTT_HIP(upload_ranks(L.Up.v, c32.data(), s));
   }
   QTT_HIP(hipMemsetAsync(L.flag, 0, sizeof(int), s));
 
@@ -259,10 +271,11 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
     return QTT_OK;
   };
   QTT_HIP(solve_core(0));
-  double J = 0.0, Jprev = 0.0;
+  QTT_HIP(launch_copy_tt(L.U.v, L.Up.v, s));
+  double J = 0.0;
   int flag = 0;
   qtt_status st;
-  if ((st = read_energy(Jprev, flag)) != QTT_OK) return st;
+  if ((st = read_energy(J, flag)) != QTT_OK) return st;
   if (flag) return fail(QTT_E_INVAL, "ALS: local matrix not positive definite (is K SPD?)");
   bool converged = D == 1;
   double crit = 0.0;
@@ -281,15 +294,22 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
         QTT_HIP(solve_core(k - 1));
       }
     }
+    // relative change of u over the sweep, then keep u for the next one
+    QTT_HIP(launch_axpby(1.0, nullptr, L.U.v, -1.0, nullptr, L.Up.v, L.Dif.v, s));
+    QTT_HIP(launch_dot(L.Dif.v, L.Dif.v, L.sc + A_DD, L.dot_ws, L.dot_elems, s));
+    QTT_HIP(launch_dot(L.U.v, L.U.v, L.sc + A_UU, L.dot_ws, L.dot_elems, s));
+    QTT_HIP(launch_copy_tt(L.U.v, L.Up.v, s));
     if ((st = read_energy(J, flag)) != QTT_OK) return st;
     if (flag) return fail(QTT_E_INVAL, "ALS: local matrix not positive definite (is K SPD?)");
-    if (!std::isfinite(J)) return fail(QTT_E_NOCONV, "ALS: energy is not finite");
-    crit = std::fabs(J) > 0.0 ? std::sqrt(std::max(Jprev - J, 0.0) / std::fabs(J)) : 0.0;
+    double du[2];
+    QTT_HIP(hipMemcpyAsync(du, L.sc + A_DD, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+    QTT_HIP(hipStreamSynchronize(s));
+    if (!std::isfinite(J) || !std::isfinite(du[0])) return fail(QTT_E_NOCONV, "ALS: not finite");
+    crit = du[1] > 0.0 ? std::sqrt(std::max(du[0], 0.0) / du[1]) : 0.0;
     if (sweep < 64) R.residual_hist[sweep] = crit;
     if (trace)
-      std::fprintf(stderr, "[qtt_solve als] %.3fs sweep %d energy %.15e decrease %.3e\n", secs(),
+      std::fprintf(stderr, "[qtt_solve als] %.3fs sweep %d energy %.15e change %.3e\n", secs(),
                    sweep, J, crit);
-    Jprev = J;
     if (crit <= o->tol) converged = true;
   }
   R.outer = sweep;
@@ -336,7 +356,7 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
   R.max_rank = mr;
   R.status = converged ? QTT_OK : QTT_E_NOCONV;
   if (rep) *rep = R;
-  if (!converged) return fail(QTT_E_NOCONV, "ALS: energy decrease above tol after maxit_out sweeps");
+  if (!converged) return fail(QTT_E_NOCONV, "ALS: change of u above tol after maxit_out sweeps");
   return QTT_OK;
 }
 

@@ -322,16 +322,31 @@ __global__ void __launch_bounds__(256) k_syrk_mfma(double *A, int64_t N, int kc0
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const int rr = lane & 15, kq = lane >> 4;
   dbl4 acc00 = {0.0, 0.0, 0.0, 0.0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
-  for (int c0 = 0; c0 < kd; c0 += KC) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * KC; e += 256) {
-      const int r = e % 64, c = e / 64;
+  // thread t stages rows t%64 of depth columns t/64 + 4u (u < KC/4); the
+  // next chunk is loaded into registers while the current one is multiplied
+  constexpr int PER = 64 * KC / 256;
+  const int sr = threadIdx.x & 63, sc = threadIdx.x >> 6;
+  double pa[PER], pb[PER];
+  auto fetch = [&](int c0) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int c = sc + 4 * u;
       const bool cv = c0 + c < kd;
       const int64_t cc = N * (int64_t)(kc0 + c0 + c);
-      As[r][c] = (cv && m0 + r < N) ? A[(m0 + r) + cc] : 0.0;
-      Bs[r][c] = (cv && n0 + r < N) ? A[(n0 + r) + cc] : 0.0;
+      pa[u] = (cv && m0 + sr < N) ? A[(m0 + sr) + cc] : 0.0;
+      pb[u] = (cv && n0 + sr < N) ? A[(n0 + sr) + cc] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int c0 = 0; c0 < kd; c0 += KC) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      As[sr][sc + 4 * u] = pa[u];
+      Bs[sr][sc + 4 * u] = pb[u];
     }
     __syncthreads();
+    if (c0 + KC < kd) fetch(c0 + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       const double a0 = As[wr + rr][kk + kq], a1 = As[wr + 16 + rr][kk + kq];
@@ -363,17 +378,18 @@ constexpr int BWD_COLS = 128;
 __global__ void __launch_bounds__(256) k_bwd(const double *A, int64_t N, int k0, int kb,
                                              double *z, double *y) {
   __shared__ double Ls[CB][CB + 1];
-  __shared__ double ys[CB];
+  __shared__ double ys[CB], rd[CB];
   for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
     const int i = e % kb, j = e / kb;
     Ls[i][j] = (i >= j) ? A[(k0 + i) + N * (k0 + j)] : 0.0;
   }
+  if (threadIdx.x < kb) rd[threadIdx.x] = 1.0 / A[(k0 + threadIdx.x) + N * (k0 + threadIdx.x)];
   __syncthreads();
   if (threadIdx.x < 64) {
     const int l = threadIdx.x;
     double v = l < kb ? z[k0 + l] : 0.0;
     for (int j = kb - 1; j >= 0; --j) {
-      const double yj = __shfl(v, j, 64) / Ls[j][j];
+      const double yj = __shfl(v, j, 64) * rd[j];
       if (l == j) v = yj;
       else if (l < j) v = fma(-Ls[j][l], yj, v);
     }
