@@ -106,3 +106,55 @@ def test_als_rejects_bad_options(P):
         P.solve(K, f, P.SolveOpts(rmax=8, maxit_out=4, method="als", compute="f32"))
     with pytest.raises(P.QttError):
         P.solve(K, f, P.SolveOpts(rmax=1000, maxit_out=4, method="als"))
+
+
+def _tt_entries(cores, index):
+    """Entries of a TT vector (first core least significant) at the given
+    flat indices: a product of core slices per index."""
+    index = np.asarray(index, dtype=np.int64)
+    M = np.ones((index.size, 1))
+    stride = 1
+    for G in cores:
+        n = G.shape[1]
+        ik = (index // stride) % n
+        M = np.einsum("sa,sab->sb", M, np.transpose(G[:, ik, :], (1, 0, 2)))
+        stride *= n
+    return M[:, 0]
+
+
+def test_als_level10_matches_sampled_direct_solve(P):
+    """Full size of the level-10 traction workload (2,097,152 dofs, rank cap
+    64, eps 1e-8, the options bench.py times): the ALS solution at 2048
+    seeded entries against the oracle's sparse direct solve (stored by
+    tests/golden/make_level10_samples.py), and the energy-norm error from
+    the energy identity J(u) - J(u*) = ||u - u*||_K^2 / 2 with
+    J(u*) = -<f, u*>/2."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "level10_traction_samples.json")))
+    prob = W.cantilever_traction(10)
+    K, f = P.assemble(prob)
+    opts = P.SolveOpts(tol=1e-6, eps=1e-8, rmax=64, maxit_out=12, method="als", seed=1)
+    print("als level 10 rank 64", flush=True)
+    u, rep = P.solve(K, f, opts)
+    assert rep["status"] == 0, rep
+    cores = P.tt_to_cores(u)
+    got = _tt_entries(cores, gold["index"])
+    ref = np.asarray(gold["value"])
+    rel_l2 = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    rel_max = np.abs(got - ref).max() / gold["max_abs"]
+    Ku = P.matvec(K, u)
+    J = 0.5 * P.dot(u, Ku) - P.dot(f, u)
+    Jstar = -0.5 * gold["f_dot_u"]
+    e_energy = np.sqrt(max(2.0 * (J - Jstar), 0.0) / gold["f_dot_u"])
+    print("level 10: sampled rel l2 %.3e, rel max %.3e, energy-norm rel %.3e, sweeps %d"
+          % (rel_l2, rel_max, e_energy, rep["outer"]), flush=True)
+    # eps = 1e-8 rounding of the result alone may move it by 1e-8 relative
+    # (Frobenius); the sweeps stop at a change of 1e-6 per sweep with the
+    # change shrinking by > 10x per sweep near convergence
+    assert rel_l2 <= 2e-8, rel_l2
+    assert rel_max <= 1e-7, rel_max
+    # the energy difference resolves the energy-norm error only down to
+    # sqrt(FP64 round-off of J) ~ 1e-7
+    assert e_energy <= 1e-6, e_energy
