@@ -272,10 +272,11 @@ typedef struct {
  * of rmax): each core in turn minimises the energy <u, K u>/2 - <u, f>
  * with the other cores fixed and orthogonal (a dense SPD local system of
  * r_k n_k r_{k+1} unknowns solved by Cholesky), sweeping left-right and back;
- * stop when the relative change of u over a sweep, ||u_s - u_{s-1}|| /
- * ||u_s|| (formed as a difference train), is <= tol (criterion = that
- * change, one entry of residual_hist per sweep), at most maxit_out sweeps;
- * eps > 0 then rounds u (exact rounding).
+ * stop when the change of u over a sweep, bounded by the sum of the local
+ * changes ||y_k - x_k|| (exact per core: the frames are orthonormal),
+ * relative to ||u||, is <= tol (criterion = that bound, one entry of
+ * residual_hist per sweep), at most maxit_out sweeps; eps > 0 then rounds u
+ * (exact rounding).
  * Local systems, QR and the final residual are FP64 (compute must be
  * QTT_F64); precond, eps_in, rmax_in, red_in, maxit_in, check_every and
  * sketch are unused; seed selects the random start cores when x0 is NULL

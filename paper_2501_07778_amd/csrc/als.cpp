@@ -16,12 +16,14 @@
 //   * the active core moves by a QR (forward) or LQ (backward) step that
 //     passes the triangular factor into the next core, leaving u unchanged.
 // After a local solve J(u) = -<y, g_k>/2, so the energy is known after every
-// sweep without a global product; it can only decrease (it is traced).  The
-// sweeps stop when the relative change of u over a sweep,
-// ||u_s - u_{s-1}|| / ||u_s||, falls to tol; the difference is formed as a
-// train (core concatenation) and its norm taken directly, so the criterion
-// resolves changes down to round-off (an energy difference would not: it is
-// quadratic in the change and cancels at FP64 precision near 1e-7).
+// sweep without a global product; it can only decrease (it is traced).
+// Because the frames are orthonormal, replacing core k by y changes u by
+// exactly ||y - x_k|| (x_k the core before the solve), so the sum of these
+// over a sweep bounds ||u_s - u_{s-1}|| from above (triangle inequality).
+// The sweeps stop when that sum, relative to ||u|| = ||y|| at the last
+// solve, falls to tol.  The criterion resolves changes down to round-off (an
+// energy difference would not: it is quadratic in the change and cancels at
+// FP64 precision near 1e-7).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -47,16 +49,15 @@ struct AlsLayout {
   double *sc = nullptr;           // device scalars
   int *flag = nullptr;            // Cholesky breakdown
   RoundWs rw;                     // final rounding at eps
-  TTDesc Up, Dif;                 // iterate of the previous sweep, u - u_prev
-  double *dot_ws = nullptr;
-  int64_t dot_elems = 0;
   TTDesc Ku, Rs;                  // residual check: K u and f - K u
   double *dense = nullptr, *full_ws = nullptr;
   int64_t N = 0;
   int32_t *rk_in = nullptr;       // device ranks of the packed K, f, x0
 };
 
-enum { A_YG = 0, A_FN2 = 2, A_RES = 4, A_DD = 6, A_UU = 7, A_COUNT = 8 };
+// device scalars: energy, ||f||^2, residual, then per local solve of a
+// sweep the pair (||y - x_k||^2, ||y||^2)
+enum { A_YG = 0, A_FN2 = 2, A_RES = 4, A_LOC = 8 };
 
 bool carve_als(Arena &ar, const qtt_tt *K, const qtt_tt *f, const qtt_solve_opts *o,
                AlsLayout &L) {
@@ -87,15 +88,9 @@ bool carve_als(Arena &ar, const qtt_tt *K, const qtt_tt *f, const qtt_solve_opts
   L.tmp = (double *)ar.take(sizeof(double) * nmax);
   L.Rq = (double *)ar.take(sizeof(double) * rmax * rmax);
   L.tau = (double *)ar.take(sizeof(double) * rmax);
-  L.sc = (double *)ar.take(sizeof(double) * A_COUNT);
+  L.sc = (double *)ar.take(sizeof(double) * (A_LOC + 2 * (D + 1)));
   L.flag = (int *)ar.take(sizeof(int) * 4);
   ok = round_ws_take(ar, L.U.v, L.rw) && ok;
-  ok = arena_tt(ar, L.Up, D, n, nullptr, c) && ok;
-  std::vector<int> dc(c);
-  for (int k = 1; k < D; ++k) dc[k] = 2 * c[k];
-  ok = arena_tt(ar, L.Dif, D, n, nullptr, dc) && ok;
-  L.dot_elems = std::max(dot_ws_elems(L.Dif.v, L.Dif.v), dot_ws_elems(L.U.v, L.U.v));
-  L.dot_ws = (double *)ar.take(sizeof(double) * L.dot_elems);
   // residual: K u has ranks R_k c_k, f - K u has f's ranks added
   std::vector<int> pc(c), rc(c);
   for (int k = 0; k <= D; ++k) {
@@ -199,7 +194,6 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
   {
     std::vector<int32_t> c32(c.begin(), c.end());
     QTT_HIP(upload_ranks(L.U.v, c32.data(), s));
-    QTT_HIP(upload_ranks(L.Up.v, c32.data(), s));
   }
   QTT_HIP(hipMemsetAsync(L.flag, 0, sizeof(int), s));
 
@@ -242,14 +236,20 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
                           c[k + 1], RF[k + 1], s);
   };
   int solves = 0;
-  auto solve_core = [&](int k) -> hipError_t {
+  // slot: index of the solve within its sweep (its change lands in A_LOC)
+  auto solve_core = [&](int k, int slot) -> hipError_t {
     hipError_t e = als_local_system(L.PK[k], kc(k), L.PK[k + 1], L.PF[k], fc(k), L.PF[k + 1], L.T,
                                     L.B, L.g, c[k], RK[k], n[k], RK[k + 1], c[k + 1], RF[k],
                                     RF[k + 1], s);
     if (e != hipSuccess) return e;
     const int64_t N = csize(k);
+    if ((e = hipMemcpyAsync(L.tmp, core(k), sizeof(double) * N, hipMemcpyDeviceToDevice, s)) !=
+        hipSuccess)
+      return e;
     ++solves;
-    return als_cholesky_solve(L.B, N, L.g, core(k), L.flag, L.sc + A_YG, s);
+    if ((e = als_cholesky_solve(L.B, N, L.g, core(k), L.flag, L.sc + A_YG, s)) != hipSuccess)
+      return e;
+    return launch_diff_norm2(core(k), L.tmp, N, L.sc + A_LOC + 2 * slot, s);
   };
 
   // right-orthogonalise cores D-1..1, then the environments from the right
@@ -270,8 +270,7 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
     J = -0.5 * yg;
     return QTT_OK;
   };
-  QTT_HIP(solve_core(0));
-  QTT_HIP(launch_copy_tt(L.U.v, L.Up.v, s));
+  QTT_HIP(solve_core(0, 0));
   double J = 0.0;
   int flag = 0;
   qtt_status st;
@@ -285,27 +284,26 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
       for (int k = 0; k + 1 < D; ++k) {
         QTT_HIP(qr_step(k));
         QTT_HIP(env_left(k));
-        QTT_HIP(solve_core(k + 1));
+        QTT_HIP(solve_core(k + 1, k));
       }
     } else {
       for (int k = D - 1; k >= 1; --k) {
         QTT_HIP(lq_step(k));
         QTT_HIP(env_right(k));
-        QTT_HIP(solve_core(k - 1));
+        QTT_HIP(solve_core(k - 1, D - 1 - k));
       }
     }
-    // relative change of u over the sweep, then keep u for the next one
-    QTT_HIP(launch_axpby(1.0, nullptr, L.U.v, -1.0, nullptr, L.Up.v, L.Dif.v, s));
-    QTT_HIP(launch_dot(L.Dif.v, L.Dif.v, L.sc + A_DD, L.dot_ws, L.dot_elems, s));
-    QTT_HIP(launch_dot(L.U.v, L.U.v, L.sc + A_UU, L.dot_ws, L.dot_elems, s));
-    QTT_HIP(launch_copy_tt(L.U.v, L.Up.v, s));
+    // change of u over the sweep: sum of the local changes over ||u||
+    std::vector<double> loc(2 * (D - 1));
+    QTT_HIP(hipMemcpyAsync(loc.data(), L.sc + A_LOC, sizeof(double) * 2 * (D - 1),
+                           hipMemcpyDeviceToHost, s));
     if ((st = read_energy(J, flag)) != QTT_OK) return st;
     if (flag) return fail(QTT_E_INVAL, "ALS: local matrix not positive definite (is K SPD?)");
-    double du[2];
-    QTT_HIP(hipMemcpyAsync(du, L.sc + A_DD, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
-    QTT_HIP(hipStreamSynchronize(s));
-    if (!std::isfinite(J) || !std::isfinite(du[0])) return fail(QTT_E_NOCONV, "ALS: not finite");
-    crit = du[1] > 0.0 ? std::sqrt(std::max(du[0], 0.0) / du[1]) : 0.0;
+    double dsum = 0.0;
+    for (int j = 0; j < D - 1; ++j) dsum += std::sqrt(std::max(loc[2 * j], 0.0));
+    const double unorm = std::sqrt(std::max(loc[2 * (D - 2) + 1], 0.0));
+    if (!std::isfinite(J) || !std::isfinite(dsum)) return fail(QTT_E_NOCONV, "ALS: not finite");
+    crit = unorm > 0.0 ? dsum / unorm : 0.0;
     if (sweep < 64) R.residual_hist[sweep] = crit;
     if (trace)
       std::fprintf(stderr, "[qtt_solve als] %.3fs sweep %d energy %.15e change %.3e\n", secs(),
