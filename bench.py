@@ -214,16 +214,17 @@ def small_solve(P, torch, level: int, method: str):
                 solution_max_rank=rep["max_rank"])
 
 
-def level10_solve(P, torch, level: int):
+def level10_solve(P, torch, level: int, ramp: bool = True):
     """The level-10 configuration of the plain method: the traction workload
     of the step, eps 1e-8, rank cap 64, solved by one-site ALS sweeps (FP64
-    local Cholesky solves) until the change of u over a sweep falls to 1e-6
-    relative; solves/s of one solve after a warm-up solve, the FP64 dense
+    local Cholesky solves; 3 sweeps each at ranks 16 and 32, then rank 64)
+    until the change of u over a sweep falls to 1e-6 relative; solves/s of one solve after a warm-up solve, the FP64 dense
     residual and the final rank."""
     import workloads as W
     prob = W.cantilever_traction(level)
     K, f = P.assemble(prob)
-    opts = P.SolveOpts(tol=1e-6, eps=EPS, rmax=RANK, maxit_out=12, method="als", seed=1)
+    opts = P.SolveOpts(tol=1e-6, eps=EPS, rmax=RANK, rmax_in=16 if ramp else 0, maxit_out=16,
+                       method="als", seed=1)
     ws = P._lib._workspace(P.solve_workspace_bytes(K, f, opts))
     P.solve(K, f, opts, ws=ws)
     torch.cuda.synchronize()
@@ -232,7 +233,9 @@ def level10_solve(P, torch, level: int):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return dict(workload="unit square level %d (%d dofs), seeded 8-mode traction, eps %.0e, "
-                "rank cap %d, one-site ALS" % (level, 2 * 4 ** level, EPS, RANK),
+                "rank cap %d, one-site ALS (%s)" % (level, 2 * 4 ** level, EPS, RANK,
+                                                     "rank ramp 16, 32, %d" % RANK if ramp
+                                                     else "fixed rank %d" % RANK),
                 solves_per_s=round(1.0 / dt, 4), ms_per_solve=round(1e3 * dt, 1),
                 sweeps=rep["outer"], local_solves=rep["inner"], status=rep["status"],
                 change_last_sweep=float("%.3e" % rep["criterion"]),
@@ -288,6 +291,7 @@ def main():
     solve5 = small_solve(P, torch, 5, "als") if args.solve else None
     solve5_fcg = small_solve(P, torch, 5, "fcg") if args.solve else None
     solve10 = level10_solve(P, torch, args.level) if args.solve else None
+    solve10_fixed = level10_solve(P, torch, args.level, ramp=False) if args.solve else None
     line = {
         "metric": "QTT solves/sec and matvec+round GB/s at rel. err 1e-6 vs FP64 plain GPU",
         "value": round(value, 3),
@@ -308,7 +312,8 @@ def main():
                                   EPS, RANK, ELL),
                    "bytes_per_step": nbytes, "result_ranks_max": max(y.ranks),
                    "mixed_precision": mixed, "batched_steps": batched, "solve_level5": solve5, "solve_level5_fcg": solve5_fcg,
-                   "solve_level%d" % args.level: solve10},
+                   "solve_level%d" % args.level: solve10,
+                   "solve_level%d_fixed_rank" % args.level: solve10_fixed},
         "roofline": roof,
     }
     if not args.no_cpu:

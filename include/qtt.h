@@ -276,11 +276,13 @@ typedef struct {
  * changes ||y_k - x_k|| (exact per core: the frames are orthonormal),
  * relative to ||u||, is <= tol (criterion = that bound, one entry of
  * residual_hist per sweep), at most maxit_out sweeps; eps > 0 then rounds u
- * (exact rounding).
+ * (exact rounding).  rmax_in < rmax ramps the rank: 3 sweeps at rmax_in,
+ * 3 at 2 rmax_in, ... (each stage zero-pads the cores of the last), then
+ * sweeps at rmax until tol; maxit_out counts the sweeps of all stages.
  * Local systems, QR and the final residual are FP64 (compute must be
- * QTT_F64); precond, eps_in, rmax_in, red_in, maxit_in, check_every and
- * sketch are unused; seed selects the random start cores when x0 is NULL
- * (x0 is zero-padded to the ranks).  The workspace holds one local matrix
+ * QTT_F64); precond, eps_in, red_in, maxit_in, check_every and sketch are
+ * unused; seed selects the random start cores when x0 is NULL (x0 is
+ * zero-padded to the ranks of the first stage that holds it).  The workspace holds one local matrix
  * (8 (r n r)^2 bytes at the widest core).  rmax <= 512.
  * CHEBYSHEV: u_{k+1} = u_k + d_k with d_k = c1 d_{k-1} + c2 round(C r_k),
  * r_k = round(f - K u_k) recomputed from u_k at every step (so rounding

@@ -162,7 +162,22 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
   if (!carve_als(ar, K, f, o, L)) return fail(QTT_E_CAPACITY, "solve workspace too small");
   const int D = K->ncores;
   const int32_t *n = K->nrow;
-  const std::vector<int> &c = L.caps;
+  // rank ramp: stages at rmax_in, 2 rmax_in, ... then rmax (cheap sweeps at
+  // low rank find the subspace; the local solves cost O((r n r)^3))
+  std::vector<int> stage_r;
+  if (o->rmax_in > 0 && o->rmax_in < o->rmax)
+    for (int r = o->rmax_in; r < o->rmax; r *= 2) stage_r.push_back(r);
+  stage_r.push_back(o->rmax);
+  size_t st0 = 0;
+  if (x0)  // start at the first stage whose caps hold x0
+    while (st0 + 1 < stage_r.size()) {
+      const std::vector<int> cs = bounded_caps(D, n, nullptr, stage_r[st0]);
+      bool fits = true;
+      for (int k = 0; k <= D; ++k) fits = fits && x0->ranks[k] <= cs[k];
+      if (fits) break;
+      ++st0;
+    }
+  std::vector<int> c = bounded_caps(D, n, nullptr, stage_r[st0]);
   const int32_t *RK = K->ranks, *RF = f->ranks;
   const std::vector<int64_t> koff = packed_offsets(K), foff = packed_offsets(f);
   auto core = [&](int k) { return L.U.v.data + L.U.v.off[k]; };
@@ -252,13 +267,10 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
     return launch_diff_norm2(core(k), L.tmp, N, L.sc + A_LOC + 2 * slot, s);
   };
 
-  // right-orthogonalise cores D-1..1, then the environments from the right
-  for (int k = D - 1; k >= 1; --k) QTT_HIP(lq_step(k));
   QTT_HIP(als_fill_value(L.PK[0], 1, 1.0, s));
   QTT_HIP(als_fill_value(L.PF[0], 1, 1.0, s));
   QTT_HIP(als_fill_value(L.PK[D], 1, 1.0, s));
   QTT_HIP(als_fill_value(L.PF[D], 1, 1.0, s));
-  for (int k = D - 1; k >= 1; --k) QTT_HIP(env_right(k));
 
   qtt_solve_report R;
   std::memset(&R, 0, sizeof(R));
@@ -270,45 +282,68 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
     J = -0.5 * yg;
     return QTT_OK;
   };
-  QTT_HIP(solve_core(0, 0));
-  double J = 0.0;
-  int flag = 0;
+  double J = 0.0, crit = 0.0;
+  int flag = 0, sweep = 0;
   qtt_status st;
-  if ((st = read_energy(J, flag)) != QTT_OK) return st;
-  if (flag) return fail(QTT_E_INVAL, "ALS: local matrix not positive definite (is K SPD?)");
-  bool converged = D == 1;
-  double crit = 0.0;
-  int sweep = 0;
-  for (sweep = 0; sweep < o->maxit_out && !converged; ++sweep) {
-    if (sweep % 2 == 0) {
-      for (int k = 0; k + 1 < D; ++k) {
-        QTT_HIP(qr_step(k));
-        QTT_HIP(env_left(k));
-        QTT_HIP(solve_core(k + 1, k));
+  bool converged = false;
+  constexpr int RAMP_SWEEPS = 3;
+  for (size_t stg = st0; stg < stage_r.size() && !converged && sweep < o->maxit_out; ++stg) {
+    const bool last = stg + 1 == stage_r.size();
+    if (stg > st0) {
+      // zero-pad every core to the next stage's caps (through the scratch)
+      const std::vector<int> cn = bounded_caps(D, n, nullptr, stage_r[stg]);
+      for (int k = 0; k < D; ++k) {
+        QTT_HIP(hipMemcpyAsync(L.tmp, core(k), sizeof(double) * csize(k),
+                               hipMemcpyDeviceToDevice, s));
+        QTT_HIP(als_pad_core(L.tmp, c[k], n[k], c[k + 1], core(k), cn[k], cn[k + 1], s));
       }
-    } else {
-      for (int k = D - 1; k >= 1; --k) {
-        QTT_HIP(lq_step(k));
-        QTT_HIP(env_right(k));
-        QTT_HIP(solve_core(k - 1, D - 1 - k));
-      }
+      c = cn;
+      std::vector<int32_t> c32(c.begin(), c.end());
+      QTT_HIP(upload_ranks(L.U.v, c32.data(), s));
     }
-    // change of u over the sweep: sum of the local changes over ||u||
-    std::vector<double> loc(2 * (D - 1));
-    QTT_HIP(hipMemcpyAsync(loc.data(), L.sc + A_LOC, sizeof(double) * 2 * (D - 1),
-                           hipMemcpyDeviceToHost, s));
+    // right-orthogonalise cores D-1..1, the environments from the right,
+    // then the first core
+    for (int k = D - 1; k >= 1; --k) QTT_HIP(lq_step(k));
+    for (int k = D - 1; k >= 1; --k) QTT_HIP(env_right(k));
+    QTT_HIP(solve_core(0, 0));
     if ((st = read_energy(J, flag)) != QTT_OK) return st;
     if (flag) return fail(QTT_E_INVAL, "ALS: local matrix not positive definite (is K SPD?)");
-    double dsum = 0.0;
-    for (int j = 0; j < D - 1; ++j) dsum += std::sqrt(std::max(loc[2 * j], 0.0));
-    const double unorm = std::sqrt(std::max(loc[2 * (D - 2) + 1], 0.0));
-    if (!std::isfinite(J) || !std::isfinite(dsum)) return fail(QTT_E_NOCONV, "ALS: not finite");
-    crit = unorm > 0.0 ? dsum / unorm : 0.0;
-    if (sweep < 64) R.residual_hist[sweep] = crit;
-    if (trace)
-      std::fprintf(stderr, "[qtt_solve als] %.3fs sweep %d energy %.15e change %.3e\n", secs(),
-                   sweep, J, crit);
-    if (crit <= o->tol) converged = true;
+    if (D == 1) {
+      converged = true;
+      break;
+    }
+    const int budget = last ? o->maxit_out - sweep : std::min(RAMP_SWEEPS, o->maxit_out - sweep);
+    for (int sw = 0; sw < budget && !converged; ++sw, ++sweep) {
+      if (sw % 2 == 0) {
+        for (int k = 0; k + 1 < D; ++k) {
+          QTT_HIP(qr_step(k));
+          QTT_HIP(env_left(k));
+          QTT_HIP(solve_core(k + 1, k));
+        }
+      } else {
+        for (int k = D - 1; k >= 1; --k) {
+          QTT_HIP(lq_step(k));
+          QTT_HIP(env_right(k));
+          QTT_HIP(solve_core(k - 1, D - 1 - k));
+        }
+      }
+      // change of u over the sweep: sum of the local changes over ||u||
+      std::vector<double> loc(2 * (D - 1));
+      QTT_HIP(hipMemcpyAsync(loc.data(), L.sc + A_LOC, sizeof(double) * 2 * (D - 1),
+                             hipMemcpyDeviceToHost, s));
+      if ((st = read_energy(J, flag)) != QTT_OK) return st;
+      if (flag) return fail(QTT_E_INVAL, "ALS: local matrix not positive definite (is K SPD?)");
+      double dsum = 0.0;
+      for (int j = 0; j < D - 1; ++j) dsum += std::sqrt(std::max(loc[2 * j], 0.0));
+      const double unorm = std::sqrt(std::max(loc[2 * (D - 2) + 1], 0.0));
+      if (!std::isfinite(J) || !std::isfinite(dsum)) return fail(QTT_E_NOCONV, "ALS: not finite");
+      crit = unorm > 0.0 ? dsum / unorm : 0.0;
+      if (sweep < 64) R.residual_hist[sweep] = crit;
+      if (trace)
+        std::fprintf(stderr, "[qtt_solve als] %.3fs rank %d sweep %d energy %.15e change %.3e\n",
+                     secs(), stage_r[stg], sweep, J, crit);
+      if (last && crit <= o->tol) converged = true;
+    }
   }
   R.outer = sweep;
   R.inner = solves;
