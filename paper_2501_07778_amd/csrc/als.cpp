@@ -168,6 +168,14 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
   if (o->rmax_in > 0 && o->rmax_in < o->rmax)
     for (int r = o->rmax_in; r < o->rmax; r *= 2) stage_r.push_back(r);
   stage_r.push_back(o->rmax);
+  // a stage whose caps (limited by the mode products) equal the next one's
+  // is not a lower rank: drop it
+  for (size_t i = 0; i + 1 < stage_r.size();) {
+    if (bounded_caps(D, n, nullptr, stage_r[i]) == bounded_caps(D, n, nullptr, stage_r[i + 1]))
+      stage_r.erase(stage_r.begin() + i);
+    else
+      ++i;
+  }
   size_t st0 = 0;
   if (x0)  // start at the first stage whose caps hold x0
     while (st0 + 1 < stage_r.size()) {
