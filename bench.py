@@ -180,6 +180,39 @@ def batched_steps(P, torch, ncases: int):
                 speedup_vs_1_worker=round(rates[1] / rates[best], 2))
 
 
+def batched_solves(P, torch, ncases: int):
+    """Solves of the batched configuration: case i (rng(1000 + i)) draws its
+    level (8..11), rank cap (16..96) and 16 load coefficients; each is solved
+    by ALS (rank ramp from 16 to the cap, tol 1e-6, eps 1e-6, at most 24
+    sweeps).  Cases run concurrently by host workers on their own streams
+    (qtt_solve_batched); solves/s at 1, 4 and 8 concurrent cases.  A case
+    whose cap is below the rank its solution needs stops at the sweep limit
+    (status QTT_E_NOCONV) with the best iterate of that rank."""
+    import workloads as W
+    probs = []
+    for i in range(ncases):
+        c = W.batch_case(i)
+        K, f = P.assemble(W.cantilever_two_component(c.level, c.coeffs))
+        opts = P.SolveOpts(tol=1e-6, eps=1e-6, rmax=c.cap, rmax_in=16, maxit_out=24,
+                           method="als", seed=1)
+        probs.append((K, f, opts))
+    batch = P.Batch(probs)
+    rates, res = {}, None
+    for conc in (1, 4, 8):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = P.solve_batched(batch, conc)
+        torch.cuda.synchronize()
+        rates[conc] = time.perf_counter() - t0
+    best = min(rates, key=rates.get)
+    return dict(cases=ncases, levels=sorted(set(W.batch_case(i).level for i in range(ncases))),
+                caps=[W.batch_case(i).cap for i in range(ncases)],
+                solves_per_s={str(k): round(ncases / v, 3) for k, v in rates.items()},
+                best_concurrency=best, speedup_vs_1=round(rates[1] / rates[best], 2),
+                converged=sum(1 for _, r in res if r["status"] == 0),
+                sweeps=[r["outer"] for _, r in res])
+
+
 def small_solve(P, torch, level: int, method: str):
     """The plain-method configuration: level-5 unit square, left edge
     clamped, body force (0, -1), eps 1e-10.  "als": one-site ALS at the
@@ -288,6 +321,7 @@ def main():
     roof = matvec_roofline(P, torch, K, x)
     mixed = mixed_precision(P, torch, K, x, ws, max(2, args.steps // 2))
     batched = batched_steps(P, torch, args.batch) if args.batch > 0 else None
+    bsolves = batched_solves(P, torch, 16) if (args.batch > 0 and args.solve) else None
     solve5 = small_solve(P, torch, 5, "als") if args.solve else None
     solve5_fcg = small_solve(P, torch, 5, "fcg") if args.solve else None
     solve10 = level10_solve(P, torch, args.level) if args.solve else None
@@ -311,7 +345,7 @@ def main():
                                % (args.level, 2 * 4 ** args.level, K.D, max(K.ranks), RANK,
                                   EPS, RANK, ELL),
                    "bytes_per_step": nbytes, "result_ranks_max": max(y.ranks),
-                   "mixed_precision": mixed, "batched_steps": batched, "solve_level5": solve5, "solve_level5_fcg": solve5_fcg,
+                   "mixed_precision": mixed, "batched_steps": batched, "batched_solves": bsolves, "solve_level5": solve5, "solve_level5_fcg": solve5_fcg,
                    "solve_level%d" % args.level: solve10,
                    "solve_level%d_fixed_rank" % args.level: solve10_fixed},
         "roofline": roof,

@@ -231,3 +231,28 @@ def test_als_lshape_level9_matches_sampled_direct_solve(P):
     assert rel_l2 <= 2e-6, rel_l2
     assert rel_max <= 1e-5, rel_max
     assert e_energy <= 1e-3, e_energy
+
+
+def test_als_batched_equals_single_solves(P):
+    """ALS cases of different levels, caps and ramps solved concurrently
+    (qtt_solve_batched, 4 cases at a time on their own streams) give the same
+    iterates as one solve at a time, and match the direct solve where the
+    cap is the full rank."""
+    cases = []
+    for i, (d, r, rin) in enumerate([(3, 8, 0), (5, 32, 8), (4, 16, 4), (6, 24, 8), (5, 12, 0)]):
+        prob = W.cantilever_two_component(d, W.batch_case(i).coeffs)
+        K, f = P.assemble(prob)
+        opts = P.SolveOpts(tol=1e-9, eps=0.0, rmax=r, rmax_in=rin, maxit_out=16, method="als",
+                           seed=i)
+        cases.append((prob, K, f, opts))
+    print("als batched: %d cases" % len(cases), flush=True)
+    res = P.solve_batched(P.Batch([c[1:] for c in cases]), 4)
+    for (prob, K, f, opts), (u, rep) in zip(cases, res):
+        u1, rep1 = P.solve(K, f, opts)
+        assert rep["status"] == rep1["status"] and rep["outer"] == rep1["outer"], (rep, rep1)
+        assert u.ranks == u1.ranks
+        a, b = T.full_vector(P.tt_to_cores(u)), T.full_vector(P.tt_to_cores(u1))
+        assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b)
+        if opts.rmax >= 2 ** prob.level:
+            uref, _ = fem.solve_problem(prob)
+            assert np.linalg.norm(a - uref) <= 1e-9 * np.linalg.norm(uref)
