@@ -247,6 +247,52 @@ def small_solve(P, torch, level: int, method: str):
                 solution_max_rank=rep["max_rank"])
 
 
+def cpu_baseline(level, nbytes, seconds):
+    """The FP64 oracle's product and exact rounding of the same workload;
+    a bounded sample: the product of all cores, then the rounding of the
+    product restricted to its first `m` cores (closed by a rank-1 end),
+    as many cores as fit in the time budget, scaled to the full train."""
+    import numpy as np
+    import workloads as W
+    from oracle import assembly as A, qtt as T
+    prob = W.cantilever_traction(level)
+    Kq, _ = A.assemble_qtt(prob)
+    modes = [2] * (2 * level + 1)
+    x = W.random_tt_cores(5, modes, W.capped_ranks(modes, RANK))
+    t0 = time.time()
+    y = T.matvec(Kq, x)
+    t_mv = time.time() - t0
+    # rounding sample: QR/SVD work is per core; time the first m cores
+    D = len(y)
+    done, t_rd = 0, 0.0
+    m = 2
+    while True:
+        sub = [c.copy() for c in y[:m]]
+        sub[-1] = sub[-1][:, :, :1]
+        t1 = time.time()
+        T.tt_round(sub, EPS, RANK)
+        dt = time.time() - t1
+        done, t_rd = m, dt
+        if t_mv + dt > seconds or m >= D:
+            break
+        m = min(D, m + 3)
+    per_step = t_mv + t_rd * (D / done)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    try:
+        import threadpoolctl
+        threads = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] or [1])
+    except ImportError:
+        threads = cores
+    return dict(value=round(nbytes / per_step / 1e9, 4), unit="GB/s",
+                cores=min(cores, threads), kind="oracle",
+                sample="oracle matvec of all %d cores (%.1f s) + exact rounding of the "
+                       "first %d cores (%.1f s), scaled to %d cores: %.1f s per step"
+                       % (D, t_mv, done, t_rd, D, per_step))
+
+
 def level10_solve(P, torch, level: int, ramp: bool = True):
     """The level-10 configuration of the plain method: the traction workload
     of the step, eps 1e-8, rank cap 64, solved by one-site ALS sweeps (FP64
