@@ -6,7 +6,7 @@
 // two small operand cores and writes an output core that is R*r times larger
 // in each rank, so it is bound by HBM writes: the kernel streams the output
 // once, fully coalesced along the fastest index b (the rank of x), with the
-// operand values kept in registers.
+// operand slices of each output column staged in LDS.
 #include <hip/hip_bf16.h>
 
 #include <algorithm>
@@ -32,10 +32,87 @@ __device__ __forceinline__ float to_compute<__hip_bfloat16>(double v) {
   return __bfloat162float(__float2bfloat16(static_cast<float>(v)));
 }
 
-// One block per output column (i, c, d) of core blockIdx.y; the P = ra0*rx0
-// rows of the column are contiguous in memory.
+// Blocks loop over the output columns (i, c, d) of core blockIdx.y; the
+// P = ra0*rx0 rows of a column are contiguous in memory.  The operand slices
+// of a column, A[:, i, :, c] (ra0 x m) and x[:, :, d] (rx0 x m), are staged
+// in LDS once, so the output loop reads no global memory and issues one
+// 16-byte non-temporal store per lane for two consecutive rows.
+constexpr int MV_SLICE = 2048;  // doubles per staged operand slice
+__global__ void __launch_bounds__(256) k_matvec_f64(TTView A, TTView x, TTView y) {
+  __shared__ double As[MV_SLICE], Xs[MV_SLICE];
+  const int k = blockIdx.y;
+  const int ra0 = A.rk[k], ra1 = A.rk[k + 1];
+  const int rx0 = x.rk[k], rx1 = x.rk[k + 1];
+  if (blockIdx.x == 0 && k == 0 && threadIdx.x <= A.D)
+    y.rk[threadIdx.x] = A.rk[threadIdx.x] * x.rk[threadIdx.x];
+  const int n = A.n[k], m = A.m[k];
+  const int P = ra0 * rx0;
+  const int ncols = n * ra1 * rx1;
+  // never write past the output slot (its caps bound the product ranks);
+  // the host picks this kernel only when the slices fit the LDS arrays
+  if (P > y.cap[k] || ra1 * rx1 > y.cap[k + 1]) return;
+  if (ra0 * m > MV_SLICE || rx0 * m > MV_SLICE) return;
+  const double *Ak = A.data + A.off[k];
+  const double *xk = x.data + x.off[k];
+  double *yk = y.data + y.off[k];
+  const int t = threadIdx.x;
+  // output pair e2 = t + 256 s covers rows e = 2 e2, 2 e2 + 1 (a = e / rx0,
+  // b = e % rx0); the step of 512 rows is q whole rows plus r
+  const int q = 512 / rx0, r = 512 % rx0;
+  for (int col = blockIdx.x; col < ncols; col += gridDim.x) {
+    const int i = col % n;
+    const int s = col / n;
+    const int c = s / rx1;
+    const int d = s - c * rx1;
+    __syncthreads();
+    for (int e = t; e < ra0 * m; e += 256) {
+      const int a = e % ra0, j = e / ra0;
+      As[e] = Ak[a + (int64_t)ra0 * (i + (int64_t)n * (j + (int64_t)m * c))];
+    }
+    for (int e = t; e < rx0 * m; e += 256) {
+      const int b = e % rx0, j = e / rx0;
+      Xs[e] = xk[b + (int64_t)rx0 * (j + (int64_t)m * d)];
+    }
+    __syncthreads();
+    double *ycol = yk + (int64_t)P * col;
+    if ((P & 1) == 0 && (((uintptr_t)ycol) & 15) == 0) {
+      int a0 = (2 * t) / rx0, b0 = 2 * t - a0 * rx0;
+      for (int e2 = t; e2 < P / 2; e2 += 256) {
+        int a1 = a0, b1 = b0 + 1;
+        if (b1 == rx0) {
+          b1 = 0;
+          ++a1;
+        }
+        double v0 = 0.0, v1 = 0.0;
+        for (int j = 0; j < m; ++j) {
+          v0 = fma(As[a0 + ra0 * j], Xs[b0 + rx0 * j], v0);
+          v1 = fma(As[a1 + ra0 * j], Xs[b1 + rx0 * j], v1);
+        }
+        typedef double d2v __attribute__((ext_vector_type(2)));
+        const d2v v = {v0, v1};
+        __builtin_nontemporal_store(v, reinterpret_cast<d2v *>(ycol) + e2);
+        a0 += q;
+        b0 += r;
+        if (b0 >= rx0) {
+          b0 -= rx0;
+          ++a0;
+        }
+      }
+    } else {
+      for (int e = t; e < P; e += 256) {
+        const int a = e / rx0, b = e - a * rx0;
+        double v = 0.0;
+        for (int j = 0; j < m; ++j) v = fma(As[a + ra0 * j], Xs[b + rx0 * j], v);
+        __builtin_nontemporal_store(v, ycol + e);
+      }
+    }
+  }
+}
+
+// The same product with the operand values read from global memory, for
+// slices too large for the LDS arrays of k_matvec_f64.
 __global__ void __launch_bounds__(MV_TX *MV_TY)
-    k_matvec_f64(TTView A, TTView x, TTView y) {
+    k_matvec_f64_direct(TTView A, TTView x, TTView y) {
   const int k = blockIdx.y;
   const int ra0 = A.rk[k], ra1 = A.rk[k + 1];
   const int rx0 = x.rk[k], rx1 = x.rk[k + 1];
@@ -387,8 +464,13 @@ hipError_t launch_matvec(const TTView &A, const TTView &x, const TTView &y,
   cols = cols < 1024 ? cols : 1024;
   dim3 grid(cols, A.D);
   dim3 block(MV_TX * MV_TY);
-  if (compute == QTT_F64)
-    hipLaunchKernelGGL(k_matvec_f64, grid, block, 0, s, A, x, y);
+  bool staged = true;
+  for (int k = 0; k < A.D; ++k)
+    staged = staged && A.cap[k] * A.m[k] <= MV_SLICE && x.cap[k] * A.m[k] <= MV_SLICE;
+  if (compute == QTT_F64 && staged)
+    hipLaunchKernelGGL(k_matvec_f64, grid, dim3(256), 0, s, A, x, y);
+  else if (compute == QTT_F64)
+    hipLaunchKernelGGL(k_matvec_f64_direct, grid, block, 0, s, A, x, y);
   else if (compute == QTT_F32)
     hipLaunchKernelGGL(k_matvec_lp<float>, grid, block, 0, s, A, x, y);
   else
