@@ -37,9 +37,27 @@ __device__ __forceinline__ float to_compute<__hip_bfloat16>(double v) {
 // of a column, A[:, i, :, c] (ra0 x m) and x[:, :, d] (rx0 x m), are staged
 // in LDS once, so the output loop reads no global memory and issues one
 // 16-byte non-temporal store per lane for two consecutive rows.
-constexpr int MV_SLICE = 2048;  // doubles per staged operand slice
-__global__ void __launch_bounds__(256) k_matvec_f64(TTView A, TTView x, TTView y) {
-  __shared__ double As[MV_SLICE], Xs[MV_SLICE];
+// T = double: FP64 throughout; T = float or __hip_bfloat16: operands rounded
+// to T when staged, products accumulated in FP32, output written in FP64.
+constexpr int MV_SLICE = 2048;  // entries per staged operand slice
+template <typename T> struct MvStage { typedef float type; };
+template <> struct MvStage<double> { typedef double type; };
+template <typename T>
+__device__ __forceinline__ typename MvStage<T>::type mv_stage(double v) {
+  return to_compute<T>(v);
+}
+template <>
+__device__ __forceinline__ double mv_stage<double>(double v) {
+  return v;
+}
+__device__ __forceinline__ double mv_fma(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float mv_fma(float a, float b, float c) { return fmaf(a, b, c); }
+
+template <typename T>
+__device__ __forceinline__ void matvec_staged(const TTView &A, const TTView &x, const TTView &y,
+                                              typename MvStage<T>::type *As,
+                                              typename MvStage<T>::type *Xs) {
+  typedef typename MvStage<T>::type S;
   const int k = blockIdx.y;
   const int ra0 = A.rk[k], ra1 = A.rk[k + 1];
   const int rx0 = x.rk[k], rx1 = x.rk[k + 1];
@@ -67,11 +85,11 @@ __global__ void __launch_bounds__(256) k_matvec_f64(TTView A, TTView x, TTView y
     __syncthreads();
     for (int e = t; e < ra0 * m; e += 256) {
       const int a = e % ra0, j = e / ra0;
-      As[e] = Ak[a + (int64_t)ra0 * (i + (int64_t)n * (j + (int64_t)m * c))];
+      As[e] = mv_stage<T>(Ak[a + (int64_t)ra0 * (i + (int64_t)n * (j + (int64_t)m * c))]);
     }
     for (int e = t; e < rx0 * m; e += 256) {
       const int b = e % rx0, j = e / rx0;
-      Xs[e] = xk[b + (int64_t)rx0 * (j + (int64_t)m * d)];
+      Xs[e] = mv_stage<T>(xk[b + (int64_t)rx0 * (j + (int64_t)m * d)]);
     }
     __syncthreads();
     double *ycol = yk + (int64_t)P * col;
@@ -83,13 +101,13 @@ __global__ void __launch_bounds__(256) k_matvec_f64(TTView A, TTView x, TTView y
           b1 = 0;
           ++a1;
         }
-        double v0 = 0.0, v1 = 0.0;
+        S v0 = 0, v1 = 0;
         for (int j = 0; j < m; ++j) {
-          v0 = fma(As[a0 + ra0 * j], Xs[b0 + rx0 * j], v0);
-          v1 = fma(As[a1 + ra0 * j], Xs[b1 + rx0 * j], v1);
+          v0 = mv_fma(As[a0 + ra0 * j], Xs[b0 + rx0 * j], v0);
+          v1 = mv_fma(As[a1 + ra0 * j], Xs[b1 + rx0 * j], v1);
         }
         typedef double d2v __attribute__((ext_vector_type(2)));
-        const d2v v = {v0, v1};
+        const d2v v = {static_cast<double>(v0), static_cast<double>(v1)};
         __builtin_nontemporal_store(v, reinterpret_cast<d2v *>(ycol) + e2);
         a0 += q;
         b0 += r;
@@ -101,12 +119,23 @@ __global__ void __launch_bounds__(256) k_matvec_f64(TTView A, TTView x, TTView y
     } else {
       for (int e = t; e < P; e += 256) {
         const int a = e / rx0, b = e - a * rx0;
-        double v = 0.0;
-        for (int j = 0; j < m; ++j) v = fma(As[a + ra0 * j], Xs[b + rx0 * j], v);
-        __builtin_nontemporal_store(v, ycol + e);
+        S v = 0;
+        for (int j = 0; j < m; ++j) v = mv_fma(As[a + ra0 * j], Xs[b + rx0 * j], v);
+        __builtin_nontemporal_store(static_cast<double>(v), ycol + e);
       }
     }
   }
+}
+
+__global__ void __launch_bounds__(256) k_matvec_f64(TTView A, TTView x, TTView y) {
+  __shared__ double As[MV_SLICE], Xs[MV_SLICE];
+  matvec_staged<double>(A, x, y, As, Xs);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_matvec_lp_staged(TTView A, TTView x, TTView y) {
+  __shared__ float As[MV_SLICE], Xs[MV_SLICE];
+  matvec_staged<T>(A, x, y, As, Xs);
 }
 
 // The same product with the operand values read from global memory, for
@@ -467,14 +496,20 @@ hipError_t launch_matvec(const TTView &A, const TTView &x, const TTView &y,
   bool staged = true;
   for (int k = 0; k < A.D; ++k)
     staged = staged && A.cap[k] * A.m[k] <= MV_SLICE && x.cap[k] * A.m[k] <= MV_SLICE;
-  if (compute == QTT_F64 && staged)
-    hipLaunchKernelGGL(k_matvec_f64, grid, dim3(256), 0, s, A, x, y);
-  else if (compute == QTT_F64)
+  if (staged) {
+    if (compute == QTT_F64)
+      hipLaunchKernelGGL(k_matvec_f64, grid, dim3(256), 0, s, A, x, y);
+    else if (compute == QTT_F32)
+      hipLaunchKernelGGL(k_matvec_lp_staged<float>, grid, dim3(256), 0, s, A, x, y);
+    else
+      hipLaunchKernelGGL(k_matvec_lp_staged<__hip_bfloat16>, grid, dim3(256), 0, s, A, x, y);
+  } else if (compute == QTT_F64) {
     hipLaunchKernelGGL(k_matvec_f64_direct, grid, block, 0, s, A, x, y);
-  else if (compute == QTT_F32)
+  } else if (compute == QTT_F32) {
     hipLaunchKernelGGL(k_matvec_lp<float>, grid, block, 0, s, A, x, y);
-  else
+  } else {
     hipLaunchKernelGGL(k_matvec_lp<__hip_bfloat16>, grid, block, 0, s, A, x, y);
+  }
   return hipGetLastError();
 }
 
