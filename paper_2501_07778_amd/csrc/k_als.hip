@@ -24,7 +24,7 @@
 namespace qtt {
 namespace {
 
-constexpr int CB = 64;       // Cholesky panel width
+constexpr int CB = 32;       // Cholesky panel width (<= 64: one wavefront per panel)
 constexpr int AWG = 256;
 
 // ---------------------------------------------------------------- envs
@@ -221,7 +221,7 @@ __global__ void k_local_g(const double *Lf, const double *F, const double *Rf, d
 // ---------------------------------------------------------------- Cholesky
 // Blocked right-looking Cholesky B = L L^T with the forward substitution
 // L z = g folded into the panel kernels, then a blocked backward
-// substitution L^T y = z.  Panels are CB = 64 columns wide; the trailing
+// substitution L^T y = z.  Panels are CB = 32 columns wide; the trailing
 // update is deferred over strips of NB = 256 columns (inner updates touch
 // only the strip), so the trailing matrix is read and written once per strip
 // by an FP64 MFMA kernel.
@@ -230,11 +230,12 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // factor the diagonal block A[k0:k0+kb, k0:k0+kb] (one wavefront, lane i
 // holds row i in registers; the active column is broadcast through LDS),
-// then z1 = L11^-1 g1 in place in g.  Lanes >= kb carry an identity row.
+// then z1 = L11^-1 g1 in place in g.  Lanes kb..CB-1 carry an identity row,
+// lanes >= CB a zero row.
 // *flag becomes 1 when a pivot is not positive.
 __global__ void __launch_bounds__(64) k_potrf_fwd(double *A, int64_t N, int k0, int kb, double *g,
                                                   int *flag) {
-  __shared__ double col[CB];
+  __shared__ double col[64];  // one entry per lane; lanes >= CB carry zero rows
   const int i = threadIdx.x;
   const bool live = i < kb;
   double x[CB];
@@ -283,7 +284,7 @@ __global__ void __launch_bounds__(64) k_trsm_fwd(double *A, int64_t N, int k0, d
     const int i = e % CB, j = e / CB;
     Lt[i][j] = (i >= j) ? A[(k0 + i) + N * (k0 + j)] : 0.0;
   }
-  zs[threadIdx.x] = g[k0 + threadIdx.x];
+  if (threadIdx.x < CB) zs[threadIdx.x] = g[k0 + threadIdx.x];
   __syncthreads();
   const int64_t row = (int64_t)k0 + CB + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (row >= N) return;
@@ -372,7 +373,7 @@ __global__ void __launch_bounds__(256) k_syrk_mfma(double *A, int64_t N, int kc0
 // backward substitution step for the block [k0, k0+kb): every workgroup
 // solves L_bb^T y_b = z_b (one wavefront, shuffles), workgroup 0 stores y_b,
 // and each workgroup then updates its 128 entries of z below k0:
-// z_i -= sum_j L[k0+j, i] y_j (8 lanes per i reading the 64 contiguous
+// z_i -= sum_j L[k0+j, i] y_j (8 lanes per i reading the CB contiguous
 // entries of column i's block row).
 constexpr int BWD_COLS = 128;
 __global__ void __launch_bounds__(256) k_bwd(const double *A, int64_t N, int k0, int kb,
