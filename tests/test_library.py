@@ -58,3 +58,38 @@ def test_host_validation_without_gpu():
     # a workspace that is too small is reported, not used
     assert L.qtt_round(C.byref(t), 1e-8, 0, None, None, None, 16, None) == -3
     assert L.qtt_version().startswith(b"qtt")
+
+
+def test_als_options_and_workspace_on_the_host():
+    """The ALS method's option checks and workspace query (host only: the
+    descriptors' device pointers are never dereferenced).  The workspace
+    holds one dense local matrix, 8 (r n r)^2 bytes at the widest core."""
+    if not os.path.exists(LIB):
+        pytest.skip("libqtt.so not built")
+    import paper_2501_07778_amd as P
+    L = P.lib()
+    D = 21
+    nrow = (C.c_int32 * D)(*([2] * D))
+    kr = [1, 4, 14, 23] + [25] * 14 + [20, 16, 4, 1]
+    fr = [1, 2, 4, 8] + [12] * 14 + [8, 4, 2, 1]
+    kranks = (C.c_int32 * (D + 1))(*kr)
+    franks = (C.c_int32 * (D + 1))(*fr)
+    K = P._lib._TT(D, nrow, nrow, kranks, 4096, 1 << 30)
+    f = P._lib._TT(D, nrow, None, franks, 8192, 1 << 30)
+
+    def ws(**kw):
+        o = P.SolveOpts(method="als", **kw).c()
+        need = C.c_size_t()
+        st = L.qtt_solve_workspace(C.byref(K), C.byref(f), C.byref(o), C.byref(need))
+        return st, need.value
+
+    st64, b64 = ws(rmax=64, maxit_out=8)
+    st32, b32 = ws(rmax=32, maxit_out=8)
+    assert st64 == 0 and st32 == 0
+    assert b64 >= 8 * (64 * 2 * 64) ** 2          # the local matrix at N = 8192
+    # the local matrix grows as (r n r)^2 (the residual check's trains as r)
+    assert b64 - b32 >= 8 * ((64 * 2 * 64) ** 2 - (32 * 2 * 32) ** 2)
+    assert ws(rmax=64, maxit_out=0)[0] == -1       # no sweeps
+    assert ws(rmax=1000, maxit_out=8)[0] == -1     # rank beyond the supported cap
+    assert ws(rmax=64, maxit_out=8, compute="f32")[0] == -7   # local solves are FP64
+    assert b"FP64" in L.qtt_last_error()
