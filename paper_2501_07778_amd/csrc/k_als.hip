@@ -11,10 +11,11 @@
 //   g[(a,i,b)]           = sum_{c,d} Lf[a,c] F_k[c,i,d] Rf[b,d],
 // with L/R the left/right environments of <x, K x> and Lf/Rf those of <x, f>.
 // B is symmetric positive definite (K is, the frames are orthonormal); it is
-// factored by a blocked right-looking Cholesky (64-wide panels: panel
-// factorisation in one workgroup, triangular solve of the panel rows, a
-// tiled trailing update).  After the solve the core is orthogonalised (QR)
-// and the environment moves one core on.
+// factored by a blocked right-looking Cholesky (CB-wide panels: the diagonal
+// block factored in one wavefront, the panel rows solved against it, the
+// forward substitution of g folded into both, an FP64 MFMA trailing update
+// deferred over strips), then solved backward.  After the solve the core is
+// orthogonalised (QR or LQ) and the environments move one core on.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
