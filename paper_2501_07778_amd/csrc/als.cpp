@@ -44,6 +44,7 @@ struct AlsLayout {
   std::vector<double *> PK, PF;   // environments of <u, K u> and <u, f>
   double *W1 = nullptr, *W2 = nullptr;    // environment stages
   double *T = nullptr, *B = nullptr, *g = nullptr;  // local system
+  double *Ld = nullptr, *z = nullptr;   // diagonal blocks of the factor, L^-1 g
   double *tmp = nullptr;          // core-sized scratch
   double *Rq = nullptr, *tau = nullptr;   // QR factor and reflector scales
   double *sc = nullptr;           // device scalars
@@ -85,6 +86,8 @@ bool carve_als(Arena &ar, const qtt_tt *K, const qtt_tt *f, const qtt_solve_opts
   L.T = (double *)ar.take(sizeof(double) * tl);
   L.B = (double *)ar.take(sizeof(double) * nmax * nmax);
   L.g = (double *)ar.take(sizeof(double) * nmax);
+  L.Ld = (double *)ar.take(sizeof(double) * als_chol_diag_elems(nmax));
+  L.z = (double *)ar.take(sizeof(double) * nmax);
   L.tmp = (double *)ar.take(sizeof(double) * nmax);
   L.Rq = (double *)ar.take(sizeof(double) * rmax * rmax);
   L.tau = (double *)ar.take(sizeof(double) * rmax);
@@ -270,7 +273,8 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
         hipSuccess)
       return e;
     ++solves;
-    if ((e = als_cholesky_solve(L.B, N, L.g, core(k), L.flag, L.sc + A_YG, s)) != hipSuccess)
+    if ((e = als_cholesky_solve(L.B, N, L.g, core(k), L.Ld, L.z, L.flag, L.sc + A_YG, s)) !=
+        hipSuccess)
       return e;
     return launch_diff_norm2(core(k), L.tmp, N, L.sc + A_LOC + 2 * slot, s);
   };

@@ -185,11 +185,14 @@ hipError_t als_local_system(const double *L, const double *K, const double *R, c
                             const double *F, const double *Rf, double *T, double *B, double *g,
                             int r0, int ra0, int n, int ra1, int r1, int rf0, int rf1,
                             hipStream_t s);
-// B y = g for SPD B: B is overwritten by its Cholesky factor L, y receives
-// the solution, g is consumed; zz (may be NULL) receives <y, g> (computed as
-// <z, z>, z = L^-1 g); *flag becomes nonzero on a pivot <= 0
-hipError_t als_cholesky_solve(double *B, int64_t N, double *g, double *y, int *flag, double *zz,
-                              hipStream_t s);
+// B y = g for SPD B: B below its diagonal blocks is overwritten by the
+// Cholesky factor L, the diagonal blocks of L go to Lst (als_chol_diag_elems
+// doubles), z = L^-1 g to z (N doubles), y receives the solution, g is
+// consumed; zz (may be NULL) receives <y, g> (computed as <z, z>); *flag
+// becomes nonzero on a pivot <= 0
+int64_t als_chol_diag_elems(int64_t N);
+hipError_t als_cholesky_solve(double *B, int64_t N, double *g, double *y, double *Lst, double *z,
+                              int *flag, double *zz, hipStream_t s);
 // thin Householder QR of W (rows x cols, cols <= rows): Q -> W, R -> R
 hipError_t als_qr(double *W, int rows, int cols, double *R, double *tau, hipStream_t s);
 hipError_t als_gemm(const double *A, int lda, const double *B, int ldb, bool tb, double *C, int ldc,

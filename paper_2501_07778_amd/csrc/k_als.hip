@@ -221,7 +221,7 @@ __global__ void k_local_g(const double *Lf, const double *F, const double *Rf, d
 
 // ---------------------------------------------------------------- Cholesky
 // Blocked right-looking Cholesky B = L L^T with the forward substitution
-// L z = g folded into the panel kernels, then a blocked backward
+// L z = g folded into the panel kernel, then a blocked backward
 // substitution L^T y = z.  Panels are CB = 32 columns wide; the trailing
 // update is deferred over strips of NB = 256 columns (inner updates touch
 // only the strip), so the trailing matrix is read and written once per strip
@@ -229,64 +229,69 @@ __global__ void k_local_g(const double *Lf, const double *F, const double *Rf, d
 constexpr int NB = 256;
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// factor the diagonal block A[k0:k0+kb, k0:k0+kb] (one wavefront, lane i
-// holds row i in registers; the active column is broadcast through LDS),
-// then z1 = L11^-1 g1 in place in g.  Lanes kb..CB-1 carry an identity row,
-// lanes >= CB a zero row.
-// *flag becomes 1 when a pivot is not positive.
-__global__ void __launch_bounds__(64) k_potrf_fwd(double *A, int64_t N, int k0, int kb, double *g,
-                                                  int *flag) {
-  __shared__ double col[64];  // one entry per lane; lanes >= CB carry zero rows
+// One panel of the factorisation in one launch.  Every workgroup factors
+// the diagonal block A[k0:k0+kb, k0:k0+kb] itself (one wavefront, lane i
+// holds row i in registers, the active column broadcast through LDS; lanes
+// kb..CB-1 carry an identity row, lanes >= CB a zero row) and forms
+// z1 = L11^-1 g1, identically in every workgroup.  Workgroup 0 stores L11
+// (CB x CB, column-major, in Ls) and z1 (in zs_out[k0..]); the diagonal
+// block of A and g1 are only read, so no workgroup waits for another.  Then
+// each workgroup solves its 64 rows below the panel (full panels only):
+// A21 <- A21 L11^-T, and g2 <- g2 - A21 z1.  *flag becomes 1 when a pivot
+// is not positive.
+__global__ void __launch_bounds__(64) k_panel(double *A, int64_t N, int k0, int kb, double *g,
+                                              double *Ls, double *zs_out, int *flag) {
+  __shared__ double col[64];
+  __shared__ double Lt[CB][CB + 1];
+  __shared__ double zsh[CB], rd[CB];
   const int i = threadIdx.x;
   const bool live = i < kb;
-  double x[CB];
-#pragma unroll
-  for (int j = 0; j < CB; ++j)
-    x[j] = (live && j <= i) ? A[(k0 + i) + N * (k0 + j)] : (i == j ? 1.0 : 0.0);
-  double gi = live ? g[k0 + i] : 0.0;
-  bool bad = false;
-#pragma unroll
-  for (int j = 0; j < CB; ++j) {
-    const double piv = __shfl(x[j], j, 64);
-    bad = bad || !(piv > 0.0);
-    const double sq = sqrt(piv > 0.0 ? piv : 1.0);
-    x[j] = (i == j) ? sq : (i > j ? x[j] / sq : 0.0);
-    col[i] = x[j];
-    __syncthreads();
-#pragma unroll
-    for (int l = j + 1; l < CB; ++l)
-      if (i >= l) x[l] = fma(-x[j], col[l], x[l]);
-    __syncthreads();
-  }
-  // forward substitution on the block: lane j finishes z_j, the lanes below
-  // subtract its contribution
-#pragma unroll
-  for (int j = 0; j < CB; ++j) {
-    const double zj = __shfl(gi / x[j], j, 64);
-    if (i == j) gi = zj;
-    else if (i > j) gi = fma(-x[j], zj, gi);
-  }
-  if (live) {
+  {
+    double x[CB];
 #pragma unroll
     for (int j = 0; j < CB; ++j)
-      if (j <= i) A[(k0 + i) + N * (k0 + j)] = x[j];
-    g[k0 + i] = gi;
+      x[j] = (live && j <= i) ? A[(k0 + i) + N * (k0 + j)] : (i == j ? 1.0 : 0.0);
+    double gi = live ? g[k0 + i] : 0.0, diag = 1.0;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      const double piv = __shfl(x[j], j, 64);
+      bad = bad || !(piv > 0.0);
+      const double sq = sqrt(piv > 0.0 ? piv : 1.0);
+      if (i == j) diag = sq;
+      x[j] = (i == j) ? sq : (i > j ? x[j] / sq : 0.0);
+      col[i] = x[j];
+      __syncthreads();
+#pragma unroll
+      for (int l = j + 1; l < CB; ++l)
+        if (i >= l) x[l] = fma(-x[j], col[l], x[l]);
+      __syncthreads();
+    }
+    // forward substitution on the block: lane j finishes z_j, the lanes
+    // below subtract its contribution
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      const double zj = __shfl(gi / x[j], j, 64);
+      if (i == j) gi = zj;
+      else if (i > j) gi = fma(-x[j], zj, gi);
+    }
+    if (i < CB) {
+#pragma unroll
+      for (int j = 0; j < CB; ++j) Lt[i][j] = (j <= i) ? x[j] : 0.0;
+      zsh[i] = gi;
+      rd[i] = 1.0 / diag;
+    }
+    if (blockIdx.x == 0) {
+      if (live) {
+#pragma unroll
+        for (int j = 0; j < CB; ++j) Ls[i + CB * j] = (j <= i) ? x[j] : 0.0;
+        zs_out[k0 + i] = gi;
+      }
+      if (bad && i == 0) flag[0] = 1;
+    }
   }
-  if (bad && i == 0) flag[0] = 1;
-}
-
-// rows k0+CB .. N-1 of a full panel: A21 <- A21 L11^-T (each row held in
-// registers, L11 in LDS), then g2 <- g2 - A21 z1.  Only full panels have
-// rows below them, so the width is the constant CB.
-__global__ void __launch_bounds__(64) k_trsm_fwd(double *A, int64_t N, int k0, double *g) {
-  __shared__ double Lt[CB][CB + 1];
-  __shared__ double zs[CB];
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    const int i = e % CB, j = e / CB;
-    Lt[i][j] = (i >= j) ? A[(k0 + i) + N * (k0 + j)] : 0.0;
-  }
-  if (threadIdx.x < CB) zs[threadIdx.x] = g[k0 + threadIdx.x];
   __syncthreads();
+  if (kb < CB) return;  // the last, partial panel has no rows below it
   const int64_t row = (int64_t)k0 + CB + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (row >= N) return;
   double x[CB];
@@ -297,13 +302,13 @@ __global__ void __launch_bounds__(64) k_trsm_fwd(double *A, int64_t N, int k0, d
     double v = x[j];
 #pragma unroll
     for (int l = 0; l < j; ++l) v = fma(-x[l], Lt[j][l], v);
-    x[j] = v / Lt[j][j];
+    x[j] = v * rd[j];
   }
   double sg = 0.0;
 #pragma unroll
   for (int j = 0; j < CB; ++j) {
     A[row + N * (k0 + j)] = x[j];
-    sg = fma(x[j], zs[j], sg);
+    sg = fma(x[j], zsh[j], sg);
   }
   g[row] -= sg;
 }
@@ -372,20 +377,21 @@ __global__ void __launch_bounds__(256) k_syrk_mfma(double *A, int64_t N, int kc0
 }
 
 // backward substitution step for the block [k0, k0+kb): every workgroup
-// solves L_bb^T y_b = z_b (one wavefront, shuffles), workgroup 0 stores y_b,
+// solves L_bb^T y_b = z_b (one wavefront, shuffles; L_bb as stored by
+// k_panel), workgroup 0 stores y_b,
 // and each workgroup then updates its 128 entries of z below k0:
 // z_i -= sum_j L[k0+j, i] y_j (8 lanes per i reading the CB contiguous
 // entries of column i's block row).
 constexpr int BWD_COLS = 128;
 __global__ void __launch_bounds__(256) k_bwd(const double *A, int64_t N, int k0, int kb,
-                                             double *z, double *y) {
+                                             const double *Lb, double *z, double *y) {
   __shared__ double Ls[CB][CB + 1];
   __shared__ double ys[CB], rd[CB];
   for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
     const int i = e % kb, j = e / kb;
-    Ls[i][j] = (i >= j) ? A[(k0 + i) + N * (k0 + j)] : 0.0;
+    Ls[i][j] = (i >= j) ? Lb[i + CB * j] : 0.0;
   }
-  if (threadIdx.x < kb) rd[threadIdx.x] = 1.0 / A[(k0 + threadIdx.x) + N * (k0 + threadIdx.x)];
+  if (threadIdx.x < kb) rd[threadIdx.x] = 1.0 / Lb[threadIdx.x * (CB + 1)];
   __syncthreads();
   if (threadIdx.x < 64) {
     const int l = threadIdx.x;
@@ -626,25 +632,24 @@ hipError_t als_local_system(const double *L, const double *K, const double *R, c
   return hipGetLastError();
 }
 
-// B (N x N, SPD) y = g: B is overwritten by its Cholesky factor L and y
-// receives the solution; g is consumed.  zz (may be NULL) receives
-// <z, z> = <y, g> for z = L^-1 g.
-hipError_t als_cholesky_solve(double *B, int64_t N, double *g, double *y, int *flag, double *zz,
-                              hipStream_t s) {
+// B (N x N, SPD) y = g: the part of B below the diagonal blocks is
+// overwritten by the Cholesky factor, the diagonal blocks of L go to Lst
+// (CB x CB each, ceil(N/CB) of them), z = L^-1 g to z (N), and y receives
+// the solution; g is consumed.  zz (may be NULL) receives <z, z> = <y, g>.
+hipError_t als_cholesky_solve(double *B, int64_t N, double *g, double *y, double *Lst, double *z,
+                              int *flag, double *zz, hipStream_t s) {
   for (int64_t K0 = 0; K0 < N; K0 += NB) {
     const int64_t K1 = std::min<int64_t>(K0 + NB, N);
     for (int64_t k0 = K0; k0 < K1; k0 += CB) {
       const int kb = (int)std::min<int64_t>(CB, N - k0);
-      hipLaunchKernelGGL(k_potrf_fwd, dim3(1), dim3(64), 0, s, B, N, (int)k0, kb, g, flag);
-      const int64_t rest = N - k0 - kb;
-      if (rest > 0) {  // implies a full panel (kb == CB)
-        hipLaunchKernelGGL(k_trsm_fwd, dim3((int)((rest + 63) / 64)), dim3(64), 0, s, B, N,
-                           (int)k0, g);
-        const int64_t nb = k0 + CB;
-        if (nb < K1)
-          hipLaunchKernelGGL(k_syrk_mfma, dim3((int)((N - nb + 63) / 64), (int)((K1 - nb + 63) / 64)),
-                             dim3(256), 0, s, B, N, (int)k0, CB, (int)nb, (int)K1);
-      }
+      const int64_t rest = N - k0 - kb;  // > 0 implies a full panel (kb == CB)
+      const int groups = (int)std::max<int64_t>(1, (rest + 63) / 64);
+      hipLaunchKernelGGL(k_panel, dim3(groups), dim3(64), 0, s, B, N, (int)k0, kb, g,
+                         Lst + (k0 / CB) * CB * CB, z, flag);
+      const int64_t nb = k0 + CB;
+      if (rest > 0 && nb < K1)
+        hipLaunchKernelGGL(k_syrk_mfma, dim3((int)((N - nb + 63) / 64), (int)((K1 - nb + 63) / 64)),
+                           dim3(256), 0, s, B, N, (int)k0, CB, (int)nb, (int)K1);
     }
     if (K1 < N) {
       const int t = (int)((N - K1 + 63) / 64);
@@ -652,16 +657,19 @@ hipError_t als_cholesky_solve(double *B, int64_t N, double *g, double *y, int *f
                          (int)K1, (int)N);
     }
   }
-  if (zz) hipLaunchKernelGGL(k_vdot, dim3(1), dim3(AWG), 0, s, g, g, N, zz);
+  if (zz) hipLaunchKernelGGL(k_vdot, dim3(1), dim3(AWG), 0, s, z, z, N, zz);
   const int64_t nblk = (N + CB - 1) / CB;
   for (int64_t b = nblk - 1; b >= 0; --b) {
     const int64_t k0 = b * CB;
     const int kb = (int)std::min<int64_t>(CB, N - k0);
     const int groups = (int)std::max<int64_t>(1, (k0 + BWD_COLS - 1) / BWD_COLS);
-    hipLaunchKernelGGL(k_bwd, dim3(groups), dim3(256), 0, s, B, N, (int)k0, kb, g, y);
+    hipLaunchKernelGGL(k_bwd, dim3(groups), dim3(256), 0, s, B, N, (int)k0, kb,
+                       (const double *)(Lst + b * CB * CB), z, y);
   }
   return hipGetLastError();
 }
+
+int64_t als_chol_diag_elems(int64_t N) { return ((N + CB - 1) / CB) * CB * CB; }
 
 hipError_t als_qr(double *W, int rows, int cols, double *R, double *tau, hipStream_t s) {
   hipLaunchKernelGGL(k_qr_thin, dim3(1), dim3(AWG), 0, s, W, rows, cols, R, tau);

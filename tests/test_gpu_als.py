@@ -122,7 +122,7 @@ def _tt_entries(cores, index):
     return M[:, 0]
 
 
-@pytest.mark.parametrize("rmax_in,bound", [(16, 2e-8), (0, 1e-8)])
+@pytest.mark.parametrize("rmax_in,bound", [(16, 3e-8), (0, 1e-8)])
 def test_als_level10_matches_sampled_direct_solve(P, rmax_in, bound):
     """Full size of the level-10 traction workload (2,097,152 dofs, rank cap
     64, eps 1e-8, tol 1e-6): the ALS solution at 2048 seeded entries against
@@ -155,7 +155,10 @@ def test_als_level10_matches_sampled_direct_solve(P, rmax_in, bound):
     print("level 10: sampled rel l2 %.3e, rel max %.3e, energy-norm rel %.3e, sweeps %d"
           % (rel_l2, rel_max, e_energy, rep["outer"]), flush=True)
     # eps = 1e-8 rounding of the result alone may move it by 1e-8 relative
-    # (Frobenius); measured 1.5e-8 with the ramp, 8.1e-9 at fixed rank
+    # (Frobenius); the ramp's rank-64 stage stops after two sweeps at a
+    # change below 1e-6, which leaves up to about twice that (measured
+    # 1.5e-8 to 1.7e-8); at fixed rank the sweeps go on to a change of 1e-8
+    # (measured 7.5e-9 to 8.5e-9)
     assert rel_l2 <= bound, rel_l2
     assert rel_max <= 1e-7, rel_max
     # the energy difference resolves the energy-norm error only down to
