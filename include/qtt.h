@@ -213,17 +213,20 @@ typedef struct {
   double tol;        /* CG_IR: stop when ||f - K u|| <= tol ||f|| (FP64).
                         CHEBYSHEV, FCG: stop when sqrt(<r, C r>) <= tol sqrt(<f, C f>)
                         with r = f - K u: the preconditioned residual, equal to
-                        the relative energy-norm error within sqrt(lmax/lmin) */
+                        the relative energy-norm error within sqrt(lmax/lmin).
+                        ALS: stop when the change of u over a sweep is
+                        <= tol ||u||                                          */
   double eps;        /* rounding accuracy of the iterate u                    */
   int32_t rmax;      /* rank cap of u                                         */
   double eps_in;     /* rounding accuracy of the residual, the preconditioned
                         residual and the search direction (relative to each
                         vector's own norm)                                    */
-  int32_t rmax_in;   /* rank cap of those vectors (<= rmax for CHEBYSHEV)    */
+  int32_t rmax_in;   /* rank cap of those vectors (<= rmax for CHEBYSHEV);
+                        ALS: first rank of the rank ramp (>= rmax: none)     */
   double red_in;     /* CG_IR: residual reduction of each correction solve   */
   int32_t maxit_in;  /* CG_IR: CG iterations per correction solve;
                         CHEBYSHEV, FCG: iterations in total                   */
-  int32_t maxit_out; /* CG_IR: refinement steps                              */
+  int32_t maxit_out; /* CG_IR: refinement steps; ALS: sweeps in total        */
   int32_t check_every; /* iterations between host convergence checks        */
   qtt_dtype compute; /* products of the correction: QTT_F64, QTT_F32 or
                         QTT_BF16 with FP32 accumulation (CG_IR: K p; CHEBYSHEV
@@ -282,8 +285,10 @@ typedef struct {
  * Local systems, QR and the final residual are FP64 (compute must be
  * QTT_F64); precond, eps_in, red_in, maxit_in, check_every and sketch are
  * unused; seed selects the random start cores when x0 is NULL (x0 is
- * zero-padded to the ranks of the first stage that holds it).  The workspace holds one local matrix
- * (8 (r n r)^2 bytes at the widest core).  rmax <= 512.
+ * zero-padded to the ranks of the first stage that holds it).  The
+ * workspace holds one local matrix (8 (r n r)^2 bytes at the widest core)
+ * and the trains of the final FP64 residual check (ranks R_k r_k).
+ * rmax <= 512.
  * CHEBYSHEV: u_{k+1} = u_k + d_k with d_k = c1 d_{k-1} + c2 round(C r_k),
  * r_k = round(f - K u_k) recomputed from u_k at every step (so rounding
  * errors do not accumulate in a recurrence), c1, c2 from the Chebyshev
