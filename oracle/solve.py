@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-The paper solves K u = f with AMEn (Sec. 3.5 and Sec. 4), which it cites but
+The paper solves K u = f with AMEn (Sec. 3, Sec. 3.7 and Sec. 4), which it cites but
 does not describe.  The solve here is driven by the same two operations the
 paper's format provides, the QTT matrix-vector product and TT rounding:
 
