@@ -71,7 +71,7 @@ typedef struct {
 /* ------------------------------------------------------------ problem
  * One square subdomain [x0, x0+side] x [y0, y0+side] carrying 2^level nodes
  * per side (Sec. 3.2).  fixed[s][c] != 0 clamps component c (0 = x, 1 = y)
- * on side s (0 = west, 1 = east, 2 = south, 3 = north) (Sec. 3.6).        */
+ * on side s (0 = west, 1 = east, 2 = south, 3 = north) (Sec. 3.8).        */
 typedef struct {
   double x0, y0, side;
   uint8_t fixed[4][2];
@@ -95,7 +95,7 @@ typedef struct {
   const qtt_traction *trac;
   int32_t coupling;         /* q > 1: 0 = symmetric exact coupling (copy
                                averaging plus copy Laplacian), 1 = the
-                               paper's coupling rows (Sec. 3.5.1); the
+                               paper's coupling rows (Sec. 3.6.1); the
                                latter is not symmetric and is for assembly
                                only                                        */
 } qtt_problem;

@@ -266,7 +266,7 @@ def _touch(sm, sp):
 
 def connectivity(prob, m: int, p: int) -> Cores:
     """Pi^(mp): rows on subdomain m, columns on p, 1 where nodes coincide
-    (Sec. 3.5.1), identity on the component digit."""
+    (Sec. 3.6.1), identity on the component digit."""
     d, q = prob.level, prob.q
     t = _touch(prob.subs[m], prob.subs[p])
     if t == "none":

@@ -227,7 +227,7 @@ def body_load(d: int, M: sp.spmatrix, body) -> np.ndarray:
 
 
 def dirichlet_mask(d: int, sq) -> np.ndarray:
-    """1 for free dofs, 0 for dofs clamped by ``sq.fixed`` (Sec. 3.6)."""
+    """1 for free dofs, 0 for dofs clamped by ``sq.fixed`` (Sec. 3.8)."""
     n = 2 ** d
     m = np.ones(2 * n * n)
     for s in range(4):
@@ -244,7 +244,7 @@ def interface_pairs(prob):
 
     Returns a list of (g_a, g_b) canonical replicated dof pairs with a from
     the lower-numbered subdomain; two nodes match when their coordinates
-    coincide (the connectivity matrices Pi^(mp) of Sec. 3.5.1)."""
+    coincide (the connectivity matrices Pi^(mp) of Sec. 3.6.1)."""
     d = prob.level
     n = 2 ** d
     coords = []
@@ -333,11 +333,11 @@ def assemble_system(prob, coupling: str = "symmetric"):
     coupling = "symmetric": K = T Kbd T + gamma L_Gamma, f = T fbd.
     coupling = "paper": row block m holds K^(m) U^(m) + sum_p Pi^(mp) K^(p)
     U^(p) + gamma (D_m U^(m) - sum_p Pi^(mp) U^(p)) and the load
-    f^(m) + sum_p Pi^(mp) f^(p) (Sec. 3.5.1 with the multiplier sign of the
+    f^(m) + sum_p Pi^(mp) f^(p) (Sec. 3.6.1 with the multiplier sign of the
     solution-concatenation subsection).
     gamma is the mean diagonal of the subdomain stiffness K^(1).
     Dirichlet: K_bc = P K P + gamma_D (I - P), f_bc = P f, P = diag(mask),
-    gamma_D the mean diagonal of the coupled K (Sec. 3.6).
+    gamma_D the mean diagonal of the coupled K (Sec. 3.8).
     """
     Kbd, fbd, mask, K1 = assemble_replicated(prob)
     N = Kbd.shape[0]

@@ -1,7 +1,7 @@
 // solve.cpp — qtt_solve: iterative solvers on the QTT format driven by the
 // QTT matrix-vector product and TT rounding.
 //
-// The paper solves K u = f with AMEn (Sec. 3.5, Sec. 4), which it cites but
+// The paper solves K u = f with AMEn (Sec. 3, 3.7 and 4), which it cites but
 // does not describe; these solves are built from the two operations of the
 // format instead.
 //
