@@ -108,7 +108,7 @@ typedef struct {
  *   stiffness.
  * The stiffness uses exact 2x2 Gauss quadrature of the Q1 element integrals
  * (Sec. 3.3-3.4), the loads are mass matrices times nodal intensities
- * (eq. load:vector:intensity and its edge analogue).  Both results are
+ * (the load-vector equation of Sec. 3.5 and its edge analogue).  Both results are
  * rounded to relative accuracy `eps` (use 1e-14).
  * K: matrix with ncores = 1 + (q>1) + 2 level, nrow = ncol = modes; f: vector
  * with the same modes.  The caller provides nrow/ncol arrays and data
@@ -334,8 +334,12 @@ qtt_status qtt_solve_batched(int32_t n, qtt_solve_case *cases, int32_t concurren
 /* qtt_autotune_batched — times qtt_solve_batched on the given cases at
  * concurrency 1, 2, 4, 8, 16 and 32 (each run solves all n cases), stores
  * the fastest for the batch's largest level and returns it in *best (and
- * the solves/s of each candidate in rates[6] when rates is not NULL).  The
- * cases' results are those of the last run.                                */
+ * the converged solves/s of each candidate in rates[6] when rates is not
+ * NULL).  A case that stops at its iteration limit (QTT_E_NOCONV) is a
+ * finished run for the timing but not a solve; any other failure stops the
+ * tuning and is returned.  The cases' results are those of the last run and
+ * the return value is their aggregate status (QTT_E_NOCONV when some case
+ * did not converge; *best is written either way).                          */
 qtt_status qtt_autotune_batched(int32_t n, qtt_solve_case *cases, int32_t *best,
                                 double *rates);
 

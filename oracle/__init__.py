@@ -9,8 +9,8 @@ which holds seeded input parameters and no arithmetic of the method.
 Modules
 -------
 fem        plain sparse Q1 finite elements: element loop with 2x2 Gauss
-           quadrature (Sec. 3.2-3.4), consistent loads (eq. load:vector:
-           intensity), Dirichlet masks (Sec. 3.8), subdomain coupling
+           quadrature (Sec. 3.2-3.4), consistent loads (the load-vector
+           equation of Sec. 3.5), Dirichlet masks (Sec. 3.8), subdomain coupling
            (Sec. 3.6.1 and the solution-concatenation subsection) and a
            sparse direct solve.
 qtt        plain tensor-train algebra on NumPy arrays: TT-SVD and TT

@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 Builds K and f directly in Z-ordered QTT form (Alg. 1), cores ordered
 [component | subdomain (q > 1) | i1 j1 i2 j2 ... id jd].  The subdomain
 stiffness is the sum over the 16 vertex pairs of shifted element integrals
-(eq. Nodal:Stiffness:Matrix and eq. Subdomain:Stiffness:Matrix); on a uniform
+(the nodal and subdomain stiffness equations of Sec. 3.5); on a uniform
 square mesh with exact 2x2 Gauss quadrature that sum equals a short sum of
 Kronecker products of three 1-D matrices on n = 2^d nodes (h = side/(n-1)):
 
@@ -209,7 +209,7 @@ def _mass_times(d: int, h: float, v: Cores) -> Cores:
 
 def load_vector(prob) -> Cores:
     """f = M fbar for the body force plus edge mass times nodal traction
-    values (eq. load:vector:intensity), per subdomain and component."""
+    values (the load-vector equation of Sec. 3.5), per subdomain and component."""
     d, q = prob.level, prob.q
     n = 2 ** d
     terms = []

@@ -110,8 +110,9 @@ def element_matrices(xy: np.ndarray, C: np.ndarray):
 
     ``xy`` holds the four vertices mapped to (-1,-1), (1,-1), (1,1), (-1,1).
     Stiffness: sum over the 2x2 tensor Gauss rule of B^T C B |J|
-    (eq. Kc1c2:def and the quadrature formula after it), with
-    B = [[Nx, 0], [0, Ny], [Ny, Nx]] per vertex (eq. B).  Mass:
+    (the element-integral definition of Sec. 3.4 and the quadrature
+    formula after it), with
+    B = [[Nx, 0], [0, Ny], [Ny, Nx]] per vertex (the strain-displacement matrix of Sec. 3.3.2).  Mass:
     sum of Phi_a Phi_b |J| (the load matrix G_{c1,c2}).  Dof order within
     the element: 2*vertex + component.
     """
@@ -199,7 +200,7 @@ def side_nodes(n: int, side: int) -> np.ndarray:
 def traction_load(d: int, sq, tr) -> np.ndarray:
     """Consistent nodal load of a traction t_c(s) = sum_k a_k sin(k pi s)
     on one side: edge mass matrix times the nodal values of t (the edge
-    analogue of eq. load:vector:intensity)."""
+    analogue of the load-vector equation of Sec. 3.5)."""
     n, h = square_nodes(d, sq.x0, sq.y0, sq.side)
     f = np.zeros(2 * n * n)
     nodes = side_nodes(n, tr.side)
@@ -216,7 +217,7 @@ def traction_load(d: int, sq, tr) -> np.ndarray:
 
 
 def body_load(d: int, M: sp.spmatrix, body) -> np.ndarray:
-    """f = M fbar for a constant body force (eq. load:vector:intensity)."""
+    """f = M fbar for a constant body force (the load-vector equation of Sec. 3.5)."""
     n = 2 ** d
     f = np.zeros(2 * n * n)
     ones = np.ones(n * n)
@@ -446,11 +447,3 @@ def lshape_unique_solution(prob):
         for c in range(2):
             out[c + 2 * (L + n * n * m)] = u[2 * g + c]
     return out
-
-
-# ------------------------------------------------------------------ metrics
-
-def energy_error(K: sp.spmatrix, u_ref: np.ndarray, u: np.ndarray) -> float:
-    """Relative error in the energy seminorm sqrt(e^T K e)/sqrt(u^T K u)."""
-    e = u - u_ref
-    return float(np.sqrt(abs(e @ (K @ e)) / abs(u_ref @ (K @ u_ref))))

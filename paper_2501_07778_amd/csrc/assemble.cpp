@@ -4,8 +4,8 @@
 // 1-D factors, and every intermediate is rounded by the library's own GPU
 // rounding.  On a uniform square mesh the element integrals of the Q1
 // stiffness with exact 2x2 Gauss quadrature, summed over the 16 vertex
-// pairs with shift matrices (eq. Nodal:Stiffness:Matrix and
-// eq. Subdomain:Stiffness:Matrix), equal Kronecker products of three 1-D
+// pairs with shift matrices (the nodal and subdomain
+// stiffness equations of Sec. 3.5), equal Kronecker products of three 1-D
 // matrices on n = 2^d nodes:
 //   S1 = int phi_a' phi_b'   ((1/h) tridiag(-1, 2, -1), end diagonals 1/h)
 //   M1 = int phi_a  phi_b    ((h/6) tridiag(1, 4, 1), end diagonals 2h/6)

@@ -88,8 +88,12 @@ extern "C" qtt_status qtt_autotune_batched(int32_t n, qtt_solve_case *cases, int
     st = run_batch(n, cases, cand[j]);
     const double dt =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (st != QTT_OK) return st;
-    const double rate = n / (dt > 0.0 ? dt : 1e-9);
+    // a case that stops at its sweep limit (QTT_E_NOCONV) is a finished
+    // run for timing; any other failure ends the tuning
+    if (st != QTT_OK && st != QTT_E_NOCONV) return st;
+    int converged = 0;
+    for (int i = 0; i < n; ++i) converged += cases[i].status == QTT_OK ? 1 : 0;
+    const double rate = converged / (dt > 0.0 ? dt : 1e-9);
     if (rates) rates[j] = rate;
     if (rate > best_rate) {
       best_rate = rate;
@@ -101,6 +105,12 @@ extern "C" qtt_status qtt_autotune_batched(int32_t n, qtt_solve_case *cases, int
     g_tuned[batch_key(n, cases)] = best_c;
   }
   if (best) *best = best_c;
+  // the cases hold the last run's results; report their aggregate status
+  for (int i = 0; i < n; ++i)
+    if (cases[i].status != QTT_OK)
+      return qtt::fail((qtt_status)cases[i].status,
+                       "case " + std::to_string(i) + " ended with status " +
+                           std::to_string(cases[i].status) + " (tuning completed)");
   return QTT_OK;
 }
 

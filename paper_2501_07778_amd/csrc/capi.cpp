@@ -60,7 +60,7 @@ bool arena_tt(Arena &ar, TTDesc &t, int D, const int32_t *n,
 }
 
 // ---------------------------------------------------------------- checks
-static qtt_status check_tt(const qtt_tt *t, const char *name, bool need_ranks) {
+qtt_status check_tt(const qtt_tt *t, const char *name, bool need_ranks) {
   if (!t) return fail(QTT_E_INVAL, std::string(name) + " is NULL");
   if (t->ncores < 1 || t->ncores > QTT_MAX_CORES)
     return fail(QTT_E_INVAL, std::string(name) + ": ncores out of range");

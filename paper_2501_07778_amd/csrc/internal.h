@@ -39,6 +39,10 @@ inline void clear_stale_error() { (void)hipGetLastError(); }
 
 void set_error(const std::string &msg);
 qtt_status fail(qtt_status st, const std::string &msg);
+// Validates a caller's train: core count and modes in range; with
+// need_ranks also boundary ranks 1, interior ranks in range, capacity for
+// the packed cores and non-NULL data.
+qtt_status check_tt(const qtt_tt *t, const char *name, bool need_ranks);
 #define QTT_HIP(call)                                                     \
   do {                                                                    \
     hipError_t e_ = (call);                                               \

@@ -214,7 +214,9 @@ qtt_status check_opts(const qtt_solve_opts *o) {
 
 qtt_status check_precond(const qtt_tt *K, const qtt_tt *C) {
   if (!C) return QTT_OK;
-  if (!C->ncol || !C->data || !C->ranks || !C->nrow || C->ncores != K->ncores)
+  qtt_status st;
+  if ((st = check_tt(C, "precond", true)) != QTT_OK) return st;
+  if (!C->ncol || C->ncores != K->ncores)
     return fail(QTT_E_INVAL, "precond must be a QTT matrix with K's cores");
   for (int k = 0; k < K->ncores; ++k)
     if (C->nrow[k] != K->nrow[k] || C->ncol[k] != K->ncol[k])
@@ -225,7 +227,10 @@ qtt_status check_precond(const qtt_tt *K, const qtt_tt *C) {
 }
 
 qtt_status check_system(const qtt_tt *K, const qtt_tt *f) {
-  if (!K || !f || !K->ncol || f->ncol) return fail(QTT_E_INVAL, "K must be a matrix, f a vector");
+  qtt_status st;
+  if ((st = check_tt(K, "K", true)) != QTT_OK) return st;
+  if ((st = check_tt(f, "f", true)) != QTT_OK) return st;
+  if (!K->ncol || f->ncol) return fail(QTT_E_INVAL, "K must be a matrix, f a vector");
   if (K->ncores != f->ncores || K->ncores < 1 || K->ncores > QTT_MAX_CORES)
     return fail(QTT_E_SHAPE, "core counts differ");
   for (int k = 0; k < K->ncores; ++k)
@@ -270,9 +275,15 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
   if ((st = check_system(K, f)) != QTT_OK) return st;
   if ((st = check_opts(o)) != QTT_OK) return st;
   if ((st = check_precond(K, o->precond)) != QTT_OK) return st;
-  if (!u || !u->data || !u->ranks || u->ncores != K->ncores) return fail(QTT_E_INVAL, "bad u");
+  if (!u || !u->data || !u->ranks || !u->nrow || u->ncores != K->ncores)
+    return fail(QTT_E_INVAL, "bad u");
+  for (int k = 0; k < K->ncores; ++k)
+    if (u->nrow[k] != K->nrow[k]) return fail(QTT_E_SHAPE, "u modes differ from K's");
   if (x0) {
-    if (x0->ncores != K->ncores || x0->ncol || !x0->data) return fail(QTT_E_SHAPE, "bad x0");
+    if ((st = check_tt(x0, "x0", true)) != QTT_OK) return st;
+    if (x0->ncores != K->ncores || x0->ncol) return fail(QTT_E_SHAPE, "bad x0");
+    for (int k = 0; k < K->ncores; ++k)
+      if (x0->nrow[k] != K->nrow[k]) return fail(QTT_E_SHAPE, "x0 modes differ from K's");
     std::vector<int> cu = bounded_caps(K->ncores, K->nrow, nullptr, o->rmax);
     for (int k = 0; k <= x0->ncores; ++k)
       if (x0->ranks[k] > cu[k])

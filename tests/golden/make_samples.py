@@ -9,6 +9,12 @@ negated minimum energy):
   (1,572,864 dofs, symmetric exact coupling, clamped bottom, seeded traction
   on the top edge).
 
+The samples are 2048 uniformly drawn dofs plus stratified ones where the
+solution is hardest to approximate: nodes on and next to the clamped edge,
+on and next to the loaded edge, around the square's corners, and for the L
+around the re-entrant corner (1, 1) and along the interfaces; "stratum"
+names each sample's group.
+
 Calls only the oracle and the shared workload generator; takes a few
 minutes per workload and a few GB of memory.  Run from the repository root:
 
@@ -31,6 +37,60 @@ NSAMPLES = 2048
 SEED = 20250107
 
 
+def _dofs(prob, sub, i, j):
+    """Z-ordered indices of both components of nodes (i, j) of subdomain
+    `sub` (index c + 2 (m + q Z(i, j)))."""
+    q = prob.q
+    z = fem.zorder(np.asarray(i), np.asarray(j), prob.level)
+    g = 2 * (sub + q * z)
+    return np.concatenate([g, g + 1])
+
+
+def _samples(prob, which, ndofs, rng):
+    n = 2 ** prob.level
+    groups = [("uniform", rng.choice(ndofs, size=NSAMPLES, replace=False))]
+
+    def edge(sub, side, count):
+        t = rng.integers(0, n, count)
+        off = rng.integers(0, 2, count)          # on the edge or one node in
+        i, j = {0: (off, t), 1: (n - 1 - off, t), 2: (t, off), 3: (t, n - 1 - off)}[side]
+        return _dofs(prob, sub, i, j)
+
+    def corner(sub, ci, cj, width):
+        a = np.arange(width)
+        i = a if ci == 0 else n - 1 - a
+        j = a if cj == 0 else n - 1 - a
+        I, J = np.meshgrid(i, j, indexing="ij")
+        return _dofs(prob, sub, I.ravel(), J.ravel())
+
+    if which == "lshape":
+        # clamped bottoms of the lower squares, the loaded top of the upper one
+        groups.append(("clamped_edge", np.concatenate([edge(0, 2, 128), edge(1, 2, 128)])))
+        groups.append(("loaded_edge", edge(2, 3, 256)))
+        # the re-entrant corner (1, 1): corner (n-1, n-1) of the first
+        # square, (0, n-1) of the second, (n-1, 0) of the third
+        groups.append(("reentrant_corner", np.concatenate(
+            [corner(0, 1, 1, 6), corner(1, 0, 1, 6), corner(2, 1, 0, 6)])))
+        # the interfaces: east side of the first square (shared with the
+        # second) and its north side (shared with the third)
+        groups.append(("interfaces", np.concatenate([edge(0, 1, 64), edge(0, 3, 64)])))
+    else:
+        groups.append(("clamped_edge", edge(0, 0, 256)))
+        groups.append(("loaded_edge", edge(0, 1, 256)))
+        groups.append(("corners", np.concatenate(
+            [corner(0, ci, cj, 4) for ci in (0, 1) for cj in (0, 1)])))
+    seen = set()
+    idx, stratum = [], []
+    for name, g in groups:
+        for v in np.asarray(g, dtype=np.int64):
+            if int(v) not in seen:
+                seen.add(int(v))
+                idx.append(int(v))
+                stratum.append(name)
+    order = np.argsort(idx, kind="stable")
+    return np.asarray(idx, dtype=np.int64)[order], [stratum[k] for k in order]
+
+
 def main(which: str):
     if which == "lshape":
         prob, name, label = W.l_shape(9), "lshape9_samples.json", "l_shape(level=9)"
@@ -39,13 +99,14 @@ def main(which: str):
         label = "cantilever_traction(level=10)"
     u, f = fem.solve_problem(prob)          # both in QTT order (first core fastest)
     rng = np.random.default_rng(SEED)
-    idx = np.sort(rng.choice(u.size, size=NSAMPLES, replace=False))
+    idx, stratum = _samples(prob, which, u.size, rng)
     out = {
         "workload": label,
         "source": "oracle.fem.solve_problem (sparse direct, FP64)",
         "ndofs": int(u.size),
         "seed": SEED,
         "index": [int(i) for i in idx],
+        "stratum": stratum,
         "value": [float(repr_v) for repr_v in u[idx]],
         "norm2": float(u @ u),
         "f_dot_u": float(f @ u),

@@ -15,7 +15,10 @@ def test_sample_fixture_is_consistent(name, ndofs):
     idx = np.asarray(g["index"])
     val = np.asarray(g["value"])
     assert g["ndofs"] == ndofs
-    assert idx.size == val.size == 2048
+    assert idx.size == val.size == len(g["stratum"]) > 2048
+    strata = set(g["stratum"])
+    assert {"uniform", "clamped_edge", "loaded_edge"} <= strata
+    assert ("reentrant_corner" in strata) == name.startswith("lshape")
     assert np.all(np.diff(idx) > 0) and idx[0] >= 0 and idx[-1] < g["ndofs"]
     # the samples are part of the whole vector
     assert float(val @ val) <= g["norm2"]

@@ -93,3 +93,40 @@ def test_als_options_and_workspace_on_the_host():
     assert ws(rmax=1000, maxit_out=8)[0] == -1     # rank beyond the supported cap
     assert ws(rmax=64, maxit_out=8, compute="f32")[0] == -7   # local solves are FP64
     assert b"FP64" in L.qtt_last_error()
+
+
+def test_solve_rejects_malformed_trains_before_any_launch():
+    """qtt_solve validates K, f, x0 and u on the host: an undersized or
+    mis-shaped start vector, or an undersized operand, is an error code
+    before any device work (the descriptors' device pointers are fake)."""
+    if not os.path.exists(LIB):
+        pytest.skip("libqtt.so not built")
+    import paper_2501_07778_amd as P
+    L = P.lib()
+    D = 5
+    nrow = (C.c_int32 * D)(*([2] * D))
+    kranks = (C.c_int32 * (D + 1))(1, 3, 3, 3, 3, 1)
+    franks = (C.c_int32 * (D + 1))(1, 2, 2, 2, 2, 1)
+    K = P._lib._TT(D, nrow, nrow, kranks, 4096, 1 << 20)
+    f = P._lib._TT(D, nrow, None, franks, 8192, 1 << 20)
+    u = P._lib._TT(D, nrow, None, (C.c_int32 * (D + 1))(*([1] * (D + 1))), 16384, 1 << 20)
+    o = P.SolveOpts(method="als", rmax=4, maxit_out=4).c()
+    rep = P._lib._SolveReport()
+
+    def solve(x0):
+        return L.qtt_solve(C.byref(K), C.byref(f), C.byref(x0) if x0 is not None else None,
+                           C.byref(o), C.byref(u), C.byref(rep), 24680, 1 << 20, None)
+
+    # x0 whose packed size exceeds its capacity
+    x0 = P._lib._TT(D, nrow, None, (C.c_int32 * (D + 1))(1, 2, 2, 2, 2, 1), 32768, 8)
+    assert solve(x0) == -3 and b"x0" in L.qtt_last_error()
+    # x0 with other modes than K
+    nrow3 = (C.c_int32 * D)(*([3] * D))
+    x0 = P._lib._TT(D, nrow3, None, (C.c_int32 * (D + 1))(1, 2, 2, 2, 2, 1), 32768, 1 << 20)
+    assert solve(x0) == -2 and b"modes" in L.qtt_last_error()
+    # x0 with a boundary rank other than 1
+    x0 = P._lib._TT(D, nrow, None, (C.c_int32 * (D + 1))(2, 2, 2, 2, 2, 1), 32768, 1 << 20)
+    assert solve(x0) == -2 and b"boundary" in L.qtt_last_error()
+    # K whose capacity is below its packed size
+    K.capacity = 10
+    assert solve(None) == -3 and b"K" in L.qtt_last_error()

@@ -92,7 +92,7 @@ def test_element_stiffness_invariants():
 
 def test_distorted_element_rigid_modes():
     """Isoparametric map on a general quadrilateral keeps the rigid-body
-    null space (eq. Kc1c2:def with the full Jacobian)."""
+    null space (the element integrals of Sec. 3.4 with the full Jacobian)."""
     C = fem.c_matrix(1.0, 0.3)
     xy = np.array([[0.0, 0.0], [1.2, 0.1], [1.0, 0.9], [-0.1, 1.1]])
     ke, _ = fem.element_matrices(xy, C)

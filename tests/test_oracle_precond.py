@@ -108,3 +108,49 @@ def test_oracle_chebyshev_matches_direct(d):
     o.maxit = 60
     _, rep_bad = S.chebyshev(Kq, fq, Cq, o)
     assert not rep_bad.converged and rep_bad.residuals[-1] > 1.0
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_oracle_fcg_untruncated_is_preconditioned_cg(d):
+    """Without truncation (every eps 0) flexible CG with one stored direction
+    is preconditioned CG: its k-th iterate equals the k-th iterate of
+    SciPy's PCG (x0 = 0, preconditioner C applied as z = C r) on the dense
+    Z-ordered system.  A wrong sign or operand in alpha or beta breaks the
+    K-conjugacy and fails this."""
+    import scipy.sparse.linalg as spla
+    prob = W.cantilever_traction(d)
+    K, f, mask, info = fem.assemble_system(prob)
+    Kq, fq = A.assemble_qtt(prob)
+    Cq = PC.bpx_qtt(prob, info["gamma_D"])
+    Kz = fem.permute_matrix_to_qtt(K, d).toarray()
+    fz = fem.to_qtt_order(f, d)
+    Cz = T.full_matrix(Cq)
+    iterates = []
+    spla.cg(Kz, fz, rtol=1e-300, atol=0.0, maxiter=8,
+            M=spla.LinearOperator(Kz.shape, matvec=lambda r: Cz @ r),
+            callback=lambda xk: iterates.append(xk.copy()))
+    assert len(iterates) == 8
+    o = S.ChebOpts(tol=0.0, eps=0.0, eps_r=0.0, eps_d=0.0)
+    for k in (1, 2, 4, 8):
+        o.maxit = k
+        u, rep = S.fcg(Kq, fq, Cq, o)
+        assert rep.inner == k
+        ref = iterates[k - 1]
+        err = np.linalg.norm(T.full_vector(u) - ref) / np.linalg.norm(ref)
+        assert err <= 1e-9, (k, err)
+
+
+@pytest.mark.parametrize("d", [3, 4])
+def test_oracle_fcg_matches_direct(d):
+    """Truncated flexible CG (rounded residual, preconditioned residual and
+    direction) reaches the direct solution to about its tolerance."""
+    prob = W.cantilever_traction(d)
+    K, f, mask, info = fem.assemble_system(prob)
+    Kq, fq = A.assemble_qtt(prob)
+    Cq = PC.bpx_qtt(prob, info["gamma_D"])
+    uref, _ = fem.solve_problem(prob)
+    o = S.ChebOpts(tol=1e-9, eps=1e-12, eps_r=1e-3, eps_d=1e-3, maxit=400)
+    u, rep = S.fcg(Kq, fq, Cq, o)
+    assert rep.converged
+    err = np.linalg.norm(T.full_vector(u) - uref) / np.linalg.norm(uref)
+    assert err <= 1e-8, err

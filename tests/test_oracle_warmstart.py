@@ -1,6 +1,6 @@
 """Pins of the warm-start oracle: the TT loss equals the dense relative
 error, its gradient and the MLP backward pass match finite differences, and
-Adam reduces the loss on a tiny problem."""
+Adam reduces the loss on a tiny problem and takes hand-computed steps."""
 import numpy as np
 import pytest
 
@@ -125,3 +125,28 @@ def test_energy_loss_matches_dense_and_finite_differences():
         fd = (WS.tt_energy_loss_grad(o + de, u, Kq, nrow, ranks)[0]
               - WS.tt_energy_loss_grad(o - de, u, Kq, nrow, ranks)[0]) / (2 * h)
         assert fd == pytest.approx(g[idx], rel=1e-5, abs=1e-8)
+
+
+def test_adam_two_steps_match_hand_computation():
+    """Adam (Kingma and Ba 2015, bias-corrected moments, b1 = 0.9,
+    b2 = 0.999, eps 1e-8, lr 0.01) on one weight and one bias, gradients
+    (2, -1/2) then (-1, 4).  Step 1: the corrected moments are g and g^2, so
+    each parameter moves by -lr g / (|g| + eps).  Step 2, weight (exact
+    fractions): m = 0.9 (0.2) + 0.1 (-1) = 2/25, m / (1 - 0.81) = 8/19;
+    v = 0.999 (0.004) + 0.001 (1) = 1249/250000, v / (1 - 0.998001) =
+    4996/1999; bias: m = 71/200 -> 71/38, v = 64999/4000000 -> 64999/7996.
+    The printed deltas are -lr (corrected m) / (sqrt(corrected v) + eps).
+    A missing bias correction or swapped b1 and b2 changes step 2."""
+    params = [[np.array([[1.0]]), np.array([0.5])]]
+    m = [[np.zeros((1, 1)), np.zeros(1)]]
+    v = [[np.zeros((1, 1)), np.zeros(1)]]
+    g1 = [[np.array([[2.0]]), np.array([-0.5])]]
+    g2 = [[np.array([[-1.0]]), np.array([4.0])]]
+    WS.adam_update(params, g1, m, v, 0, 0.01)
+    assert params[0][0][0, 0] == pytest.approx(1.0 - 0.009999999950000001, abs=1e-15)
+    assert params[0][1][0] == pytest.approx(0.5 + 0.009999999800000003, abs=1e-15)
+    WS.adam_update(params, g2, m, v, 1, 0.01)
+    assert params[0][0][0, 0] == pytest.approx(1.0 - 0.009999999950000001
+                                               - 0.002663370379756864, abs=1e-14)
+    assert params[0][1][0] == pytest.approx(0.5 + 0.009999999800000003
+                                            - 0.006553266139001128, abs=1e-14)
