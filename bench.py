@@ -16,7 +16,10 @@ Gaussian cores.  One step is the hot path of every solver iteration:
 The value is the algorithmic HBM traffic of a step (read K and x, write the
 product, read it back once in the rounding, write the result) divided by the
 step time: matvec+round GB/s.  The line also carries the roofline of the
-dominant kernel (timed with HIP events on the stream it runs on) and the
+dominant kernel, the one-workgroup truncated-SVD step of the rounding
+(timed with HIP events on the stream it runs on, during the timed steps;
+algorithmic flops from the R-SVD count of each bond's unfolding), that of
+the product kernel (HBM-bound) under config, and the
 FP64 CPU oracle timed on the same step (same inputs, same Gaussian train).
 """
 from __future__ import annotations
@@ -72,13 +75,14 @@ def step(P, K, x, y, ws, seed, compute="f64"):
     return y
 
 
-def measured_traffic():
-    """HBM bytes per launch of k_matvec_f64 from the committed counter
-    summary, or None once the kernel source has changed since."""
+def measured_traffic(summary: str, source: str):
+    """HBM bytes per launch of a kernel from its committed counter summary
+    in profiles/, or None once the kernel's source file has changed since
+    the counters were taken."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
-    summ = os.path.join(here, "profiles", "k_matvec_f64_level10_pmc.md")
-    src = os.path.join(here, "paper_2501_07778_amd", "csrc", "k_tt.hip")
+    summ = os.path.join(here, "profiles", summary)
+    src = os.path.join(here, "paper_2501_07778_amd", "csrc", source)
     try:
         txt = open(summ).read()
         sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
@@ -86,7 +90,7 @@ def measured_traffic():
         return None
     vals = dict(line.split(": ", 1) for line in txt.splitlines() if ": " in line and
                 (line.startswith("traffic_bytes") or line.startswith("source_sha1")))
-    if vals.get("source_sha1(paper_2501_07778_amd/csrc/k_tt.hip)", "").strip() != sha:
+    if vals.get("source_sha1(paper_2501_07778_amd/csrc/%s)" % source, "").strip() != sha:
         return None
     return int(vals["traffic_bytes_per_launch"])
 
@@ -109,8 +113,55 @@ def matvec_roofline(P, torch, K, x):
     nbytes = tt_bytes(K) + tt_bytes(x) + tt_bytes(y)
     gbs = nbytes / (ms * 1e-3) / 1e9
     return dict(kernel="k_matvec_f64", bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS,
-                unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
+                unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
+                traffic=measured_traffic("k_matvec_f64_level10_pmc.md", "k_tt.hip"),
                 bytes_per_launch=nbytes, ms_per_launch=round(ms, 4))
+
+
+def svd_flops(m: int, n: int) -> float:
+    """Algorithmic flops of a thin SVD with both factors of an m x n matrix
+    (Golub and Van Loan's R-SVD count, 6 M N^2 + 20 N^3 with M >= N)."""
+    M, N = max(m, n), min(m, n)
+    return 6.0 * M * N * N + 20.0 * N ** 3
+
+
+def sketch_svd_flops(K, x, y_ranks) -> float:
+    """Flops of the right-to-left SVD sweep of one step: bond k's unfolding
+    has the sketch rank l_k rows (l_k = min(ell, mode products on either
+    side, product rank R_k r_k), built up from the left as in the sketch)
+    and n_k times the final rank at k+1 columns."""
+    D = K.D
+    n = [K.nrow[k] for k in range(D)]
+    l = [1] * (D + 1)
+    for k in range(1, D):
+        left = 1
+        for j in range(k):
+            left *= n[j]
+        right = 1
+        for j in range(k, D):
+            right *= n[j]
+        l[k] = max(1, min(ELL, left, right, K.ranks[k] * x.ranks[k]))
+    lz = [1] * (D + 1)
+    for k in range(D - 1):
+        lz[k + 1] = min(lz[k] * n[k], l[k + 1])
+    return sum(svd_flops(lz[k], n[k] * y_ranks[k + 1]) for k in range(1, D))
+
+
+def dominant_roofline(P, ms_total, launches, flops_per_step, steps, traffic):
+    """k_svd_step, the step's dominant kernel (one workgroup per bond, the
+    right-to-left truncated-SVD sweep): algorithmic flops per launch over
+    its average launch time from HIP events on its stream during the timed
+    steps; bound by the FP64 vector ALU (a Jacobi SVD in LDS)."""
+    per_launch_ms = ms_total / max(launches, 1)
+    flops_per_launch = flops_per_step * steps / max(launches, 1)
+    achieved = flops_per_launch / (per_launch_ms * 1e-3) / 1e12
+    return dict(kernel="k_svd_step", bound="alu", achieved=float("%.5g" % achieved),
+                peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                frac=float("%.3g" % (achieved / FP64_PEAK_TFLOPS)), traffic=traffic,
+                launches_per_step=launches / steps,
+                ms_per_launch=round(per_launch_ms, 4),
+                flops_per_launch=round(flops_per_launch),
+                share_of_step=None)
 
 
 def rel_diff(P, a, b) -> float:
@@ -356,17 +407,27 @@ def main():
     for i in range(args.warmup):
         y = step(P, K, x, y, ws, 1000 + i)
     torch.cuda.synchronize()
+    P.kernel_timing(True)
     t0 = time.perf_counter()
     for i in range(args.steps):
         y = step(P, K, x, y, ws, i)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    svd_ms, svd_n = P.kernel_timing_read("k_svd_step")
+    sqr_ms, sqr_n = P.kernel_timing_read("k_sketch_qr")
+    P.kernel_timing(False)
     # algorithmic bytes: read K, x; write Y; read Y once; write the result
     prod = 8 * sum(K.ranks[k] * x.ranks[k] * K.nrow[k] * K.ranks[k + 1] * x.ranks[k + 1]
                    for k in range(K.D))
     nbytes = tt_bytes(K) + tt_bytes(x) + 2 * prod + tt_bytes(y)
     value = nbytes / dt / 1e9
-    roof = matvec_roofline(P, torch, K, x)
+    roof_mv = matvec_roofline(P, torch, K, x)
+    roof = dominant_roofline(P, svd_ms, svd_n, sketch_svd_flops(K, x, y.ranks), args.steps,
+                             measured_traffic("k_svd_step_level10_pmc.md", "k_round.hip"))
+    roof["share_of_step"] = round(svd_ms / args.steps / (1e3 * dt), 3)
+    roof["next_kernel"] = dict(kernel="k_sketch_qr", launches_per_step=sqr_n / args.steps,
+                               ms_per_launch=round(sqr_ms / max(sqr_n, 1), 4),
+                               share_of_step=round(sqr_ms / args.steps / (1e3 * dt), 3))
     mixed = mixed_precision(P, torch, K, x, ws, max(2, args.steps // 2))
     batched = batched_steps(P, torch, args.batch) if args.batch > 0 else None
     bsolves = batched_solves(P, torch, 16) if (args.batch > 0 and args.solve) else None
@@ -395,7 +456,8 @@ def main():
                    "bytes_per_step": nbytes, "result_ranks_max": max(y.ranks),
                    "mixed_precision": mixed, "batched_steps": batched, "batched_solves": bsolves, "solve_level5": solve5, "solve_level5_fcg": solve5_fcg,
                    "solve_level%d" % args.level: solve10,
-                   "solve_level%d_fixed_rank" % args.level: solve10_fixed},
+                   "solve_level%d_fixed_rank" % args.level: solve10_fixed,
+                   "matvec_roofline": roof_mv},
         "roofline": roof,
     }
     if not args.no_cpu:

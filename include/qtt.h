@@ -412,6 +412,17 @@ qtt_status qtt_warmstart_train_step(qtt_mlp *net, const float *a, const float *t
                                     const int32_t *ranks, const qtt_tt *metric, float lr,
                                     double *loss, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------ timing   */
+/* qtt_kernel_timing — enable (nonzero) or disable per-launch timing of the
+ * rounding's one-workgroup kernels ("k_svd_step", "k_sketch_qr",
+ * "k_qr_step"): while enabled, every launch of them is bracketed by two HIP
+ * events recorded on the stream it is launched on.  Either call clears the
+ * records.  qtt_kernel_timing_read sums the device time (ms) and counts the
+ * launches of one kernel recorded since; it waits for the recorded events.
+ * For benchmarking only: the events add a few microseconds per launch.    */
+qtt_status qtt_kernel_timing(int32_t enable);
+qtt_status qtt_kernel_timing_read(const char *kernel, double *ms, int64_t *launches);
+
 /* Thread-local text of the last error of this thread.                      */
 const char *qtt_last_error(void);
 

@@ -112,6 +112,8 @@ def load_library(path: str = LIB_PATH):
                                    vp]
     L.qtt_matvec_round_workspace.argtypes = [P(_TT), P(_TT), C.c_int32, P(sz)]
     L.qtt_dot.argtypes = [P(_TT), P(_TT), P(C.c_double), vp, sz, vp]
+    L.qtt_kernel_timing.argtypes = [C.c_int32]
+    L.qtt_kernel_timing_read.argtypes = [C.c_char_p, P(C.c_double), P(C.c_int64)]
     L.qtt_axpby.argtypes = [C.c_double, P(_TT), C.c_double, P(_TT), P(_TT), vp, sz, vp]
     L.qtt_assemble_stiffness.argtypes = [P(_Problem), C.c_double, P(_TT), P(_TT), vp, sz, vp]
     L.qtt_assemble_workspace.argtypes = [P(_Problem), P(sz), P(C.c_int64), P(C.c_int64)]
@@ -133,7 +135,7 @@ def load_library(path: str = LIB_PATH):
     L.qtt_autotune_batched.argtypes = [C.c_int32, P(_SolveCase), P(C.c_int32), P(C.c_double)]
     for name in ("qtt_matvec", "qtt_round", "qtt_round_workspace", "qtt_round_sketch",
                  "qtt_round_sketch_workspace", "qtt_matvec_round", "qtt_matvec_round_workspace",
-                 "qtt_dot", "qtt_axpby",
+                 "qtt_dot", "qtt_axpby", "qtt_kernel_timing", "qtt_kernel_timing_read",
                  "qtt_assemble_stiffness", "qtt_assemble_workspace", "qtt_assemble_bpx", "qtt_solve",
                  "qtt_solve_workspace", "qtt_solve_batched", "qtt_autotune_batched",
                  "qtt_matvec_round_batched", "qtt_warmstart_workspace", "qtt_warmstart_infer",
@@ -320,6 +322,18 @@ def dot(x: TT, y: TT) -> float:
     _check(lib().qtt_dot(C.byref(x.c), C.byref(y.c), C.byref(out),
                          C.c_void_p(_aligned_ptr(ws)), ws.numel() - 256, _stream_ptr()))
     return out.value
+
+
+def kernel_timing(enable: bool) -> None:
+    """qtt_kernel_timing: start (True) or stop per-launch event timing."""
+    _check(lib().qtt_kernel_timing(1 if enable else 0))
+
+
+def kernel_timing_read(kernel: str):
+    """qtt_kernel_timing_read: (total ms, launches) of one timed kernel."""
+    ms, n = C.c_double(), C.c_int64()
+    _check(lib().qtt_kernel_timing_read(kernel.encode(), C.byref(ms), C.byref(n)))
+    return ms.value, n.value
 
 
 def axpby(a: float, x: TT, b: float, y: TT) -> TT:

@@ -30,6 +30,7 @@ SOURCES = [
     "k_full.hip",
     "batched.cpp",
     "k_mlp.hip",
+    "ktimer.cpp",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

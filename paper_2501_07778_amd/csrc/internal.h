@@ -51,6 +51,14 @@ qtt_status check_tt(const qtt_tt *t, const char *name, bool need_ranks);
                                         hipGetErrorString(e_));           \
   } while (0)
 
+// ---------------------------------------------------------------- timing
+// Kernels that qtt_kernel_timing can time (ktimer.cpp): ktimer_begin
+// records an event on `s` before the launch and returns a handle (-1 when
+// timing is off), ktimer_end records the closing event after it.
+enum KernelTimerId { KT_SVD_STEP = 0, KT_SKETCH_QR = 1, KT_QR_STEP = 2, KT_COUNT = 3 };
+int ktimer_begin(int id, hipStream_t s);
+void ktimer_end(int handle, hipStream_t s);
+
 // ---------------------------------------------------------------- arena
 // Bump allocator over the caller's workspace; `dry` mode only counts.
 struct Arena {

@@ -723,12 +723,14 @@ hipError_t round_tt(const TTView &x, double eps, int rmax, const RoundWs &w,
     const double *src = (k == 0) ? x.data + x.off[0] : w.carry;
     const int64_t rc = (int64_t)cap_of(k) * x.n[k] * x.m[k];
     const int64_t cc = cap_of(k + 1);
+    const int th = ktimer_begin(KT_QR_STEP, s);
     if (rc * cc <= LDS_DBL && (rc < cc ? rc : cc) <= LDS_TAU)
       hipLaunchKernelGGL(k_qr_step<true>, dim3(1), dim3(WG), 0, s, x, k, src, w.work,
                          w.rbuf, tau, w.iwork);
     else
       hipLaunchKernelGGL(k_qr_step<false>, dim3(1), dim3(WG), 0, s, x, k, src, w.work,
                          w.rbuf, tau, w.iwork);
+    ktimer_end(th, s);
     const int mt = (x.cap[k + 1] + GT - 1) / GT;
     const int nt = (x.n[k + 1] * x.m[k + 1] * x.cap[k + 2] + GT - 1) / GT;
     hipLaunchKernelGGL(k_absorb, dim3(mt, nt), dim3(256), 0, s, x, k, w.rbuf,
@@ -744,12 +746,14 @@ hipError_t round_tt(const TTView &x, double eps, int rmax, const RoundWs &w,
     const int64_t nbc = r0c < ncc ? r0c : ncc;
     const int64_t mbc = r0c > ncc ? r0c : ncc;
     const bool wide_qr = r0c < ncc && mbc * nbc + 2 * nbc * nbc <= LDS_SVD;
+    const int th = ktimer_begin(KT_SVD_STEP, s);
     if ((mbc * nbc <= LDS_DBL && nbc * nbc <= LDS_DBL) || wide_qr)
       hipLaunchKernelGGL(k_svd_step<true>, dim3(1), dim3(WG), 0, s, x, k, eps, rmax,
                          w.carry, w.work, w.vbuf, w.fold, sig, w.iwork, w.scal, w.rotlog);
     else
       hipLaunchKernelGGL(k_svd_step<false>, dim3(1), dim3(WG), 0, s, x, k, eps, rmax,
                          w.carry, w.work, w.vbuf, w.fold, sig, w.iwork, w.scal, w.rotlog);
+    ktimer_end(th, s);
     const int mt = (x.cap[k - 1] * x.n[k - 1] * x.m[k - 1] + GT - 1) / GT;
     const int nt = (x.cap[k] + GT - 1) / GT;
     hipLaunchKernelGGL(k_fold, dim3(mt, nt), dim3(256), 0, s, x, k, w.fold,

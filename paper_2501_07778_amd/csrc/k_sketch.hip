@@ -430,10 +430,12 @@ hipError_t sketch_tt(const TTView &y, int ell, uint64_t seed, uint64_t call, dou
                          L.dims, L.P, L.S);
     }
     double *Q = y.data + y.off[k];
+    const int th = ktimer_begin(KT_SKETCH_QR, s);
     if ((int64_t)rows * cols <= LDS_DBL && rq <= LDS_TAU)
       hipLaunchKernelGGL(k_sketch_qr<true>, dim3(1), dim3(WG), 0, s, L.S, rows, cols, Q, L.Qw);
     else
       hipLaunchKernelGGL(k_sketch_qr<false>, dim3(1), dim3(WG), 0, s, L.S, rows, cols, Q, L.Qw);
+    ktimer_end(th, s);
     {
       const int mt = (rq + GT - 1) / GT, nt = (y.cap[k + 1] + GT - 1) / GT;
       hipLaunchKernelGGL(k_sketch_M, dim3(mt, nt), dim3(256), 0, s, y, k, lz, rq, Q, L.Z[cur],

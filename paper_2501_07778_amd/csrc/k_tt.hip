@@ -11,6 +11,7 @@
 
 #include <algorithm>
 
+#include "dev_gemm.h"
 #include "internal.h"
 
 namespace qtt {
@@ -316,6 +317,8 @@ __global__ void k_axpby(double a, const double *a_dev, TTView x, double b,
 // <x, y>: left environment Phi_{k+1} = sum_i x_k(:,i,:)^T Phi_k y_k(:,i,:),
 // computed by one block; Phi and the intermediate T live in `ws`.
 constexpr int DOT_THREADS = 1024;
+// largest intermediate (rx0 n ry1 doubles) the one-workgroup <x, y> takes
+constexpr int64_t DOT_ONE_BLOCK_MAX = 64 * 1024;
 __global__ void __launch_bounds__(DOT_THREADS)
     k_dot(TTView x, TTView y, double *out, double *ws, int64_t phi_cap) {
   double *phi = ws;
@@ -553,15 +556,74 @@ hipError_t launch_axpby(double a, const double *a_dev, const TTView &x,
   return hipGetLastError();
 }
 
+// <x, y> over the whole chip for wide trains: per core two GEMMs with
+// 64 x 64 output tiles (dev_gemm.h), ranks read from the device,
+// T = Phi_k y_k (rx0 x n ry1, K = ry0) then Phi_{k+1} = x_k^T T
+// (rx1 x ry1, K = rx0 n), Phi ping-ponging between two buffers.
+__device__ __forceinline__ bool dot_beyond(const TTView &x, const TTView &y, int k) {
+  return x.rk[k] > x.cap[k] || x.rk[k + 1] > x.cap[k + 1] || y.rk[k] > y.cap[k] ||
+         y.rk[k + 1] > y.cap[k + 1];
+}
+
+__global__ void __launch_bounds__(256) k_dot_T(TTView x, TTView y, int k, const double *phi,
+                                               double *T) {
+  if (dot_beyond(x, y, k)) return;
+  const int rx0 = x.rk[k], ry0 = y.rk[k], ry1 = y.rk[k + 1];
+  const int N = x.n[k] * x.m[k] * ry1;
+  if (blockIdx.x * dev::GT >= rx0 || blockIdx.y * dev::GT >= N) return;
+  dev::gemm_tile<false>(phi, rx0, y.data + y.off[k], ry0, T, rx0, rx0, N, ry0, blockIdx.x,
+                        blockIdx.y);
+}
+
+__global__ void __launch_bounds__(256) k_dot_P(TTView x, TTView y, int k, const double *T,
+                                               double *phin) {
+  if (dot_beyond(x, y, k)) return;
+  const int rx1 = x.rk[k + 1], ry1 = y.rk[k + 1];
+  const int K = x.rk[k] * x.n[k] * x.m[k];
+  if (blockIdx.x * dev::GT >= rx1 || blockIdx.y * dev::GT >= ry1) return;
+  dev::gemm_tile<true>(x.data + x.off[k], K, T, K, phin, rx1, rx1, ry1, K, blockIdx.x,
+                       blockIdx.y);
+}
+
+__global__ void k_dot_init(double *phi) { phi[0] = 1.0; }
+
+__global__ void k_dot_out(TTView x, TTView y, const double *phi, double *out) {
+  bool bad = false;
+  for (int k = 0; k <= x.D; ++k) bad = bad || x.rk[k] > x.cap[k] || y.rk[k] > y.cap[k];
+  *out = bad ? NAN : phi[0];
+}
+
 hipError_t launch_dot(const TTView &x, const TTView &y, double *out,
                       double *ws, int64_t ws_elems, hipStream_t s) {
-  int64_t phi_cap = 1;
+  int64_t phi_cap = 1, t_cap = 1;
   for (int k = 0; k <= x.D; ++k) {
     int64_t c = (int64_t)x.cap[k] * y.cap[k];
     phi_cap = c > phi_cap ? c : phi_cap;
   }
-  hipLaunchKernelGGL(k_dot, dim3(1), dim3(DOT_THREADS), 0, s, x, y, out, ws,
-                     phi_cap);
+  for (int k = 0; k < x.D; ++k) {
+    int64_t c = (int64_t)x.cap[k] * x.n[k] * x.m[k] * y.cap[k + 1];
+    t_cap = c > t_cap ? c : t_cap;
+  }
+  if (phi_cap + t_cap > ws_elems) return hipErrorInvalidValue;
+  // narrow trains: one workgroup walks all cores (no launch per core);
+  // wide ones (a product against a vector): two chip-wide GEMMs per core
+  if (t_cap <= DOT_ONE_BLOCK_MAX || 2 * phi_cap + t_cap > ws_elems) {
+    hipLaunchKernelGGL(k_dot, dim3(1), dim3(DOT_THREADS), 0, s, x, y, out, ws, phi_cap);
+    return hipGetLastError();
+  }
+  double *phi[2] = {ws, ws + phi_cap};
+  double *T = ws + 2 * phi_cap;
+  hipLaunchKernelGGL(k_dot_init, dim3(1), dim3(1), 0, s, phi[0]);
+  for (int k = 0; k < x.D; ++k) {
+    const int nm = x.n[k] * x.m[k];
+    const int mt = (x.cap[k] + dev::GT - 1) / dev::GT;
+    const int nt = (int)(((int64_t)nm * y.cap[k + 1] + dev::GT - 1) / dev::GT);
+    hipLaunchKernelGGL(k_dot_T, dim3(mt, nt), dim3(256), 0, s, x, y, k, phi[k & 1], T);
+    const int mt2 = (x.cap[k + 1] + dev::GT - 1) / dev::GT;
+    const int nt2 = (y.cap[k + 1] + dev::GT - 1) / dev::GT;
+    hipLaunchKernelGGL(k_dot_P, dim3(mt2, nt2), dim3(256), 0, s, x, y, k, T, phi[(k + 1) & 1]);
+  }
+  hipLaunchKernelGGL(k_dot_out, dim3(1), dim3(1), 0, s, x, y, phi[x.D & 1], out);
   return hipGetLastError();
 }
 
@@ -606,7 +668,7 @@ int64_t dot_ws_elems(const TTView &x, const TTView &y) {
     int64_t c = (int64_t)x.cap[k] * x.n[k] * x.m[k] * y.cap[k + 1];
     t_cap = c > t_cap ? c : t_cap;
   }
-  return phi_cap + t_cap;
+  return 2 * phi_cap + t_cap;   // two environment buffers and T
 }
 
 hipError_t launch_scalar(int op, double *s0, const double *s1,

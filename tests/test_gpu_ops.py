@@ -291,3 +291,19 @@ def test_headline_step_at_full_shape(P):
     # ~1e-9 (measured 5e-10); the step's own accuracy is eps = 1e-8
     assert e_vs_sketch <= 1e-8
     assert e_gpu <= 2.5 * e_exact
+
+
+def test_dot_wide_operands_against_oracle(P):
+    """<x, y> of a rank-40 train with a rank-1000 matrix-vector product
+    (level 8: the intermediates exceed what one workgroup handles, so the
+    per-core chip-wide GEMM path runs) against the oracle's dot."""
+    from oracle import assembly as A
+    Kq, _ = A.assemble_qtt(W.cantilever_traction(8))
+    modes = [2] * 17
+    x = W.random_tt_cores(61, modes, W.capped_ranks(modes, 40))
+    z = W.random_tt_cores(62, modes, W.capped_ranks(modes, 40))
+    y = T.matvec(Kq, z)
+    assert max(T.ranks(y)) * max(T.ranks(x)) * 2 > 64 * 1024
+    ref = T.dot(x, y)
+    got = P.dot(P.tt_from_cores(x), P.tt_from_cores(y))
+    assert got == pytest.approx(ref, rel=1e-11, abs=1e-12 * T.norm(x) * T.norm(y))
