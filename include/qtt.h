@@ -189,6 +189,19 @@ qtt_status qtt_matvec_round_workspace(const qtt_tt *A, const qtt_tt *x, int32_t 
 qtt_status qtt_dot(const qtt_tt *x, const qtt_tt *y, double *out, void *ws,
                    size_t ws_bytes, void *stream);
 
+/* qtt_dot_noalloc — qtt_dot for callers that cannot allocate device
+ * memory or pass a workspace (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the same kernels, with the
+ * scratch (device ranks, result, environments) in a library-owned device
+ * array of 16 MiB per GPU, held from the first call on that GPU until the
+ * process ends.  It allocates nothing.  Returns QTT_E_CAPACITY (before any
+ * device work) when the operands need more scratch than that: 2 (r_x r_y)
+ * + r_x n r_y doubles at the widest core plus 64.  Every call on one GPU
+ * shares the array: calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.  Synchronises
+ * `stream`.                                                               */
+qtt_status qtt_dot_noalloc(const qtt_tt *x, const qtt_tt *y, double *out, void *stream);
+
 /* qtt_axpby — z = a x + b y by core concatenation (ranks add): the first
  * cores sit side by side, middle cores block-diagonally, last cores stacked;
  * a and b scale the first core.  z must not alias x or y.  Writes z->ranks

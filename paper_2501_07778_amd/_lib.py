@@ -112,6 +112,7 @@ def load_library(path: str = LIB_PATH):
                                    vp]
     L.qtt_matvec_round_workspace.argtypes = [P(_TT), P(_TT), C.c_int32, P(sz)]
     L.qtt_dot.argtypes = [P(_TT), P(_TT), P(C.c_double), vp, sz, vp]
+    L.qtt_dot_noalloc.argtypes = [P(_TT), P(_TT), P(C.c_double), vp]
     L.qtt_kernel_timing.argtypes = [C.c_int32]
     L.qtt_kernel_timing_read.argtypes = [C.c_char_p, P(C.c_double), P(C.c_int64)]
     L.qtt_axpby.argtypes = [C.c_double, P(_TT), C.c_double, P(_TT), P(_TT), vp, sz, vp]
@@ -135,7 +136,8 @@ def load_library(path: str = LIB_PATH):
     L.qtt_autotune_batched.argtypes = [C.c_int32, P(_SolveCase), P(C.c_int32), P(C.c_double)]
     for name in ("qtt_matvec", "qtt_round", "qtt_round_workspace", "qtt_round_sketch",
                  "qtt_round_sketch_workspace", "qtt_matvec_round", "qtt_matvec_round_workspace",
-                 "qtt_dot", "qtt_axpby", "qtt_kernel_timing", "qtt_kernel_timing_read",
+                 "qtt_dot", "qtt_dot_noalloc", "qtt_axpby", "qtt_kernel_timing",
+                 "qtt_kernel_timing_read",
                  "qtt_assemble_stiffness", "qtt_assemble_workspace", "qtt_assemble_bpx", "qtt_solve",
                  "qtt_solve_workspace", "qtt_solve_batched", "qtt_autotune_batched",
                  "qtt_matvec_round_batched", "qtt_warmstart_workspace", "qtt_warmstart_infer",
@@ -321,6 +323,13 @@ def dot(x: TT, y: TT) -> float:
     out = C.c_double()
     _check(lib().qtt_dot(C.byref(x.c), C.byref(y.c), C.byref(out),
                          C.c_void_p(_aligned_ptr(ws)), ws.numel() - 256, _stream_ptr()))
+    return out.value
+
+
+def dot_noalloc(x: TT, y: TT) -> float:
+    """qtt_dot_noalloc: <x, y> with the library's own device scratch."""
+    out = C.c_double()
+    _check(lib().qtt_dot_noalloc(C.byref(x.c), C.byref(y.c), C.byref(out), _stream_ptr()))
     return out.value
 
 

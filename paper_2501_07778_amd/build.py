@@ -31,6 +31,7 @@ SOURCES = [
     "batched.cpp",
     "k_mlp.hip",
     "ktimer.cpp",
+    "noalloc.cpp",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
