@@ -69,25 +69,33 @@ typedef struct {
 } qtt_tt;
 
 /* ------------------------------------------------------------ problem
- * One square subdomain [x0, x0+side] x [y0, y0+side] carrying 2^level nodes
- * per side (Sec. 3.2).  fixed[s][c] != 0 clamps component c (0 = x, 1 = y)
- * on side s (0 = west, 1 = east, 2 = south, 3 = north) (Sec. 3.8).        */
+ * One subdomain carrying 2^level x 2^level nodes (Sec. 3.2): the square
+ * [x0, x0+side] x [y0, y0+side], or, when edges = (ax, ay, bx, by) is not
+ * all zero, the parallelogram {(x0, y0) + s (ax, ay) + t (bx, by)} with
+ * its nodes at s, t = i / (2^level - 1) (an affine image of the square
+ * mesh: every element has the same constant Jacobian, the case of the
+ * Jacobian expansion of Sec. 3.4 where it is exact).  fixed[s][c] != 0
+ * clamps component c (0 = x, 1 = y) on side s (0 = west s = 0, 1 = east
+ * s = 1, 2 = south t = 0, 3 = north t = 1) (Sec. 3.8).                   */
 typedef struct {
   double x0, y0, side;
   uint8_t fixed[4][2];
+  double edges[4];
 } qtt_square;
 
-/* Traction t_comp(s) = sum_{k=1..nmodes} amp[k-1] sin(k pi s) on side
- * `side` of subdomain `sub`, s in [0, 1] the normalised arclength.         */
+/* Traction t_comp(s) = constant + sum_{k=1..nmodes} amp[k-1] sin(k pi s)
+ * on side `side` of subdomain `sub`, s in [0, 1] the normalised arclength. */
 typedef struct {
   int32_t sub, side, comp, nmodes;
   const double *amp;
+  double constant;
 } qtt_traction;
 
 typedef struct {
   int32_t level;            /* d: 2^d nodes per subdomain side              */
-  int32_t q;                /* number of square subdomains (1..8)           */
-  const qtt_square *sub;    /* q squares of equal side, edge-to-edge        */
+  int32_t q;                /* number of subdomains (1..32)                 */
+  const qtt_square *sub;    /* q > 1: squares of equal side, edge-to-edge;
+                               q = 1: a square or a parallelogram          */
   double E, nu;             /* Young's modulus and Poisson's ratio (Sec. 2) */
   int32_t plane_strain;     /* 1 plane strain, 0 plane stress              */
   double body[2];           /* constant body force                          */
@@ -185,7 +193,9 @@ qtt_status qtt_matvec_round_workspace(const qtt_tt *A, const qtt_tt *x, int32_t 
                                       size_t *bytes);
 
 /* qtt_dot — <x, y> of two TT vectors of equal modes (left-to-right
- * environment sweep).  Synchronises `stream`.                              */
+ * environment sweep): the inner product of the TT format of Sec. 4, which
+ * the iterative solves use for step lengths and norms.  Synchronises
+ * `stream`.                                                                */
 qtt_status qtt_dot(const qtt_tt *x, const qtt_tt *y, double *out, void *ws,
                    size_t ws_bytes, void *stream);
 
@@ -202,12 +212,24 @@ qtt_status qtt_dot(const qtt_tt *x, const qtt_tt *y, double *out, void *ws,
  * `stream`.                                                               */
 qtt_status qtt_dot_noalloc(const qtt_tt *x, const qtt_tt *y, double *out, void *stream);
 
-/* qtt_axpby — z = a x + b y by core concatenation (ranks add): the first
+/* qtt_axpby — z = a x + b y in the TT format of Sec. 4, whose sum is a
+ * core concatenation (ranks add): the first
  * cores sit side by side, middle cores block-diagonally, last cores stacked;
  * a and b scale the first core.  z must not alias x or y.  Writes z->ranks
  * (host, no synchronisation); the workspace needs 1 KiB.                   */
 qtt_status qtt_axpby(double a, const qtt_tt *x, double b, const qtt_tt *y,
                      qtt_tt *z, void *ws, size_t ws_bytes, void *stream);
+
+/* qtt_tt_combine — z = sum_i coeffs[i] x[i] for nterms TT vectors of equal
+ * modes (at least two cores) by core concatenation (ranks add): first
+ * cores side by side, each scaled by its coefficient, middle cores
+ * block-diagonal, last cores stacked.  coeffs is a host array; z must not
+ * alias a term and needs capacity for the summed ranks, which are written
+ * to z->ranks (host, no synchronisation).  Used to form superposed
+ * solutions of a linear problem (the training targets of the learned warm
+ * start).                                                                 */
+qtt_status qtt_tt_combine(int32_t nterms, const double *coeffs, const qtt_tt *const *x,
+                          qtt_tt *z, void *stream);
 
 /* ------------------------------------------------------------ solve   */
 typedef enum {
@@ -217,9 +239,11 @@ typedef enum {
   QTT_SOLVE_FCG = 2,       /* flexible preconditioned CG (one stored direction),
                               true residual every step, exact step length
                               (needs `precond`)                                */
-  QTT_SOLVE_ALS = 3        /* one-site alternating least squares at fixed
+  QTT_SOLVE_ALS = 3,       /* one-site alternating least squares at fixed
                               ranks: the core update of the paper's AMEn
                               solver (Sec. 4) without residual enrichment   */
+  QTT_SOLVE_AMEN = 4       /* one-site ALS sweeps with residual enrichment
+                              between them: ranks adapt to the solution     */
 } qtt_solve_method;
 
 typedef struct {
@@ -270,10 +294,21 @@ typedef struct {
   int32_t max_rank;       /* largest bond rank of u                           */
   double criterion;       /* value of the stop criterion at exit              */
   double lmax;            /* CHEBYSHEV: the upper spectral bound used         */
+  int32_t warm_start;     /* 0: no x0; 1: the iteration started from
+                             alpha x0 (see qtt_solve); -1 (ALS): x0 was
+                             rejected (no component along the solution, or
+                             not finite) and the cold start ran instead    */
+  double warm_energy;     /* ALS with x0: J(alpha x0) = -<f, x0>^2 /
+                             (2 <x0, K x0>), the energy of the scaled start
+                             (the solution's is -<f, u>/2; their difference
+                             is half the squared energy-norm error of the
+                             start); 0 otherwise                           */
 } qtt_solve_report;
 
-/* qtt_solve — solve K u = f (K symmetric positive definite) on the QTT
- * format with every iterate rounded.
+/* qtt_solve — solve K u = f (K symmetric positive definite), the linear
+ * system of the discretised elasticity problem (Sec. 3.7, with the
+ * Dirichlet conditions of Sec. 3.8), on the QTT format with every iterate
+ * rounded (the paper solves it in the TT format by AMEn, Sec. 4, Sec. 5).
  * CG_IR: the outer loop forms the residual f - K u exactly (product,
  * difference), checks its FP64 norm and rounds it; the inner loop runs
  * truncated (P)CG on K e = r with its vectors rounded to (eps_in, rmax_in);
@@ -298,10 +333,29 @@ typedef struct {
  * Local systems, QR and the final residual are FP64 (compute must be
  * QTT_F64); precond, eps_in, red_in, maxit_in, check_every and sketch are
  * unused; seed selects the random start cores when x0 is NULL (x0 is
- * zero-padded to the ranks of the first stage that holds it).  The
+ * zero-padded to the ranks of the first stage that holds it).  x0 enters
+ * scaled by alpha = <f, x0> / <x0, K x0>, the minimiser of the energy
+ * J(alpha x0) = alpha^2 <x0, K x0>/2 - alpha <f, x0>; an x0 with
+ * <f, x0> = 0 (no better than no start at all) or non-finite values is
+ * rejected and the cold start runs (report warm_start = -1), so a learned
+ * start can only cost its check.  The
  * workspace holds one local matrix (8 (r n r)^2 bytes at the widest core)
  * and the trains of the final FP64 residual check (ranks R_k r_k).
  * rmax <= 512.
+ * AMEN: the solver the paper uses (Sec. 4, Sec. 5), in the form of ALS
+ * sweeps alternated with a global enrichment step (the ALS(t+z) scheme of
+ * Dolgov and Savostyanov 2014 that AMEn localises): the sweeps start at the
+ * ranks rmax_in (random cores, or x0); after every pair of sweeps the
+ * residual z = f - K u is formed exactly and rounded by a rank-(rmax_in + 8)
+ * sketch to (eps_in, rmax_in), then u <- round(u + alpha z, eps, rmax - rmax_in)
+ * with the energy-optimal alpha = <f - K u, z> / <z, K z> (three-operand
+ * inner products).  The enrichment adds the residual's directions to every
+ * core's basis and the rounding keeps only what the accuracy eps needs,
+ * so the ranks grow where the solution needs them instead of following
+ * caps.  Stop when the sweep change is <= tol and the enrichment moved u
+ * by at most tol ||u||; eps > 0 then rounds u.  rmax >= 2 rmax_in and
+ * rmax_in >= 1 are required; otherwise as ALS (FP64 local systems, the
+ * start check of x0, report fields; inner counts local solves).
  * CHEBYSHEV: u_{k+1} = u_k + d_k with d_k = c1 d_{k-1} + c2 round(C r_k),
  * r_k = round(f - K u_k) recomputed from u_k at every step (so rounding
  * errors do not accumulate in a recurrence), c1, c2 from the Chebyshev
@@ -393,7 +447,24 @@ typedef struct {
   float *params;
   float *adam_m, *adam_v; /* training only (may be NULL for inference) */
   int64_t step;
+  int32_t gemm_dtype;     /* QTT_BF16: every layer GEMM (forward and backward)
+                             rounds its operands to BF16 and accumulates in
+                             FP32 on the matrix cores; QTT_F32 (or QTT_F64,
+                             0): FP32 GEMMs.  Parameters, Adam moments,
+                             activations and gradients stay FP32.          */
+  int32_t loss;           /* QTT_LOSS_TT (0): the gauge-invariant distance of
+                             the trains (see qtt_warmstart_train_step);
+                             QTT_LOSS_CORES: ||o_j - u_j||^2 / ||u_j||^2 over
+                             the packed cores themselves, for targets brought
+                             to one gauge by qtt_tt_align (no metric);
+                             QTT_LOSS_ANGLE: 1 - <x, u>^2 / (<x, x> <u, u>)
+                             with x = TT(o_j), in the metric's norm if one is
+                             given: the squared relative error of the best
+                             multiple of x, which is the start qtt_solve
+                             makes of x (scale-invariant, gauge-invariant). */
 } qtt_mlp;
+
+enum { QTT_LOSS_TT = 0, QTT_LOSS_CORES = 1, QTT_LOSS_ANGLE = 2 };
 
 /* Number of floats in params for these layer sizes (-1 on bad input).      */
 int64_t qtt_mlp_param_count(int32_t nlayers, const int32_t *sizes);
@@ -411,7 +482,8 @@ qtt_status qtt_warmstart_infer(const qtt_mlp *net, const float *a, int32_t batch
                                void *ws, size_t ws_bytes, void *stream);
 
 /* qtt_warmstart_train_step — one Adam step (learning rate lr) on the mean
- * over the batch of the gauge-invariant loss ||TT(o_j) - u_j||^2/||u_j||^2,
+ * over the batch of the loss of net->loss; for QTT_LOSS_TT the
+ * gauge-invariant ||TT(o_j) - u_j||^2/||u_j||^2,
  * where o_j = MLP(a_j) and u_j (column j of targets, packed with the same
  * rank pattern, zero-padded) is the target train: forward pass, loss and
  * gradient through the TT inner products (FP64 environments), backward
@@ -424,6 +496,60 @@ qtt_status qtt_warmstart_train_step(qtt_mlp *net, const float *a, const float *t
                                     int32_t batch, int32_t ncores, const int32_t *nrow,
                                     const int32_t *ranks, const qtt_tt *metric, float lr,
                                     double *loss, void *ws, size_t ws_bytes, void *stream);
+
+/* qtt_warmstart_fit — trains the network natively: `epochs` passes over the
+ * n samples (a: sizes[0] x n, targets: sizes[nlayers] x n, column-major
+ * device FP32), each pass in a new seeded order (Fisher-Yates with
+ * splitmix64 from `seed`) split into n / batch full batches, one Adam step
+ * of qtt_warmstart_train_step per batch, the learning rate decaying from
+ * lr to lr_final along a half cosine over all steps.  loss_hist (host,
+ * `epochs` entries, may be NULL) receives each pass's mean batch loss.
+ * Synchronises `stream` once per pass.  Workspace: qtt_warmstart_fit_workspace. */
+qtt_status qtt_warmstart_fit(qtt_mlp *net, const float *a, const float *targets, int32_t n,
+                             int32_t batch, int32_t epochs, float lr, float lr_final,
+                             uint64_t seed, int32_t ncores, const int32_t *nrow,
+                             const int32_t *ranks, const qtt_tt *metric, double *loss_hist,
+                             void *ws, size_t ws_bytes, void *stream);
+qtt_status qtt_warmstart_fit_workspace(const qtt_mlp *net, int32_t n, int32_t batch,
+                                       int32_t ncores, const int32_t *nrow, const int32_t *ranks,
+                                       const qtt_tt *metric, size_t *bytes);
+
+/* qtt_warmstart_infer_tt — the warm start of one load: x0 (an FP64 TT
+ * vector with the given modes, capacity >= sizes[nlayers]) receives the
+ * network's output for the parameters a (sizes[0] floats, device) as the
+ * packed cores of the rank pattern `ranks`, which are written to
+ * x0->ranks.  Pass x0 to qtt_solve; the solve checks it and falls back to
+ * its cold start when x0 is no better than zero.  Workspace:
+ * qtt_warmstart_workspace(net, 1, 0, ...).                                 */
+qtt_status qtt_warmstart_infer_tt(const qtt_mlp *net, const float *a, int32_t ncores,
+                                  const int32_t *nrow, const int32_t *ranks, qtt_tt *x0,
+                                  void *ws, size_t ws_bytes, void *stream);
+
+/* qtt_tt_contract_last — evaluates a parametric train at one parameter
+ * vector: x (D >= 3 cores, FP64, device) whose last core carries a
+ * parameter index of size n = x->nrow[D-1]; y (D - 1 cores with x's first
+ * D - 1 modes) receives x's cores 0..D-3 unchanged and, as its last core,
+ * core D-2 contracted with v = X_{D-1} w (w: n weights, device memory),
+ * so that y = sum_i w_i x[..., i].  Writes y->ranks (x's first D - 1 ranks
+ * and a final 1; host, no synchronisation).  The last bond rank of x must
+ * be <= 1024.  Used for the learned warm start's targets: the solutions of
+ * the 16 unit loads as one train with the load index as its last core,
+ * rounded once, then evaluated at each load, so every target shares the
+ * same cores but the last.                                                */
+qtt_status qtt_tt_contract_last(const qtt_tt *x, const double *w, qtt_tt *y, void *stream);
+
+/* qtt_tt_align — brings the TT vector x to the gauge of ref (same modes and
+ * ranks, every inner rank <= 48, FP64, device) without changing the vector
+ * x represents: for k = D-1 down to 1, with M = X_k R_k^T (the r_k x r_k
+ * contraction of core k of x with that of ref over its mode and right
+ * index), Q = U V^T from the SVD M = U S V^T is the orthogonal matrix that
+ * brings Q^T X_k closest to R_k in the Frobenius norm; core k becomes
+ * Q^T X_k and core k-1 absorbs Q.  For trains in a right-orthogonal gauge
+ * this removes the sign and rotation freedom of the SVD, so that targets of
+ * nearby loads have nearby cores (the training targets of QTT_LOSS_CORES).
+ * A bond whose M has a singular value below 1e-13 of its largest keeps
+ * Q = I.  Enqueued on `stream`.                                            */
+qtt_status qtt_tt_align(qtt_tt *x, const qtt_tt *ref, void *stream);
 
 /* ------------------------------------------------------------ timing   */
 /* qtt_kernel_timing — enable (nonzero) or disable per-launch timing of the

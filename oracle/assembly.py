@@ -329,6 +329,10 @@ def assemble_qtt(prob, coupling: str = "symmetric"):
     (Alg. 1): K_bc = P K P + gamma_D (I - P), f_bc = P f with P = diag(mask)
     and gamma_D = trace(K)/N."""
     d, q = prob.level, prob.q
+    if any(getattr(sq, "edges", None) is not None for sq in prob.subs) or \
+            any(getattr(t, "constant", 0.0) != 0.0 for t in prob.tractions):
+        raise NotImplementedError("the QTT assembly oracle covers square subdomains and sine "
+                                  "tractions; use fem.assemble_system for the others")
     C = c_matrix(prob.E, prob.nu, prob.plane_strain)
     Kbd = block_diag_stiffness(d, q, C)
     fbd = load_vector(prob)

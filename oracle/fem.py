@@ -153,17 +153,44 @@ def square_nodes(d: int, x0: float, y0: float, side: float):
     return n, h
 
 
+def edge_vectors(sq):
+    """Images (a, b) of the parameter square's unit vectors: (side, 0) and
+    (0, side) for a square, the given edges for a parallelogram."""
+    if getattr(sq, "edges", None) is None:
+        return np.array([sq.side, 0.0]), np.array([0.0, sq.side])
+    ax, ay, bx, by = sq.edges
+    return np.array([ax, ay]), np.array([bx, by])
+
+
+def node_coords(d: int, sq):
+    """Coordinates of the 2^d x 2^d nodes in canonical order (index
+    i + n j): (x0, y0) + s a + t b with s = i / (n - 1), t = j / (n - 1)."""
+    n = 2 ** d
+    a, b = edge_vectors(sq)
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    s, t = i.ravel(order="F") / (n - 1), j.ravel(order="F") / (n - 1)
+    return sq.x0 + s * a[0] + t * b[0], sq.y0 + s * a[1] + t * b[1]
+
+
 def assemble_square(d: int, x0: float, y0: float, side: float,
-                    C: np.ndarray):
+                    C: np.ndarray, edges=None):
     """Element-loop assembly of the stiffness K^(m) and scalar mass M^(m) of
-    one square subdomain with 2^d nodes per side, canonical order."""
-    n, h = square_nodes(d, x0, y0, side)
+    one subdomain with 2^d nodes per side, canonical order: the square
+    [x0, x0+side] x [y0, y0+side], or with edges = (ax, ay, bx, by) the
+    parallelogram spanned by them (every element the same parallelogram,
+    its integrals by the 2x2 Gauss rule with the element's Jacobian)."""
+    n = 2 ** d
     nel = n - 1
     ie, je = np.meshgrid(np.arange(nel), np.arange(nel), indexing="ij")
     ie = ie.ravel()
     je = je.ravel()
-    # all elements are congruent squares: integrate once
-    xy = np.array([[0.0, 0.0], [h, 0.0], [h, h], [0.0, h]])
+    # all elements are congruent: integrate once
+    if edges is None:
+        a, b = np.array([side, 0.0]), np.array([0.0, side])
+    else:
+        a, b = np.array(edges[:2], dtype=float), np.array(edges[2:], dtype=float)
+    ea, eb = a / nel, b / nel
+    xy = np.array([[0.0, 0.0], ea, ea + eb, eb])
     ke, me = element_matrices(xy, C)
     vi = np.stack([ie, ie + 1, ie + 1, ie], axis=1)
     vj = np.stack([je, je, je + 1, je + 1], axis=1)
@@ -198,16 +225,18 @@ def side_nodes(n: int, side: int) -> np.ndarray:
 
 
 def traction_load(d: int, sq, tr) -> np.ndarray:
-    """Consistent nodal load of a traction t_c(s) = sum_k a_k sin(k pi s)
-    on one side: edge mass matrix times the nodal values of t (the edge
-    analogue of the load-vector equation of Sec. 3.5)."""
-    n, h = square_nodes(d, sq.x0, sq.y0, sq.side)
+    """Consistent nodal load of a traction t_c(s) = t0 + sum_k a_k
+    sin(k pi s) on one side: edge mass matrix times the nodal values of t
+    (the edge analogue of the load-vector equation of Sec. 3.5)."""
+    n = 2 ** d
+    a, b = edge_vectors(sq)
+    h = np.linalg.norm(b if tr.side <= 1 else a) / (n - 1)   # element edge length
     f = np.zeros(2 * n * n)
     nodes = side_nodes(n, tr.side)
     s = np.arange(n) / (n - 1)
-    tbar = np.zeros(n)
-    for k, a in enumerate(tr.amp, start=1):
-        tbar += a * np.sin(k * np.pi * s)
+    tbar = np.full(n, float(getattr(tr, "constant", 0.0)))
+    for k, amp in enumerate(tr.amp, start=1):
+        tbar += amp * np.sin(k * np.pi * s)
     me = edge_mass(np.array([0.0, 0.0]), np.array([h, 0.0]))
     for e in range(n - 1):
         loc = me @ tbar[e:e + 2]
@@ -250,12 +279,8 @@ def interface_pairs(prob):
     n = 2 ** d
     coords = []
     for m, sq in enumerate(prob.subs):
-        h = sq.side / (n - 1)
-        i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
-        L = (i + n * j).ravel()
-        x = sq.x0 + h * i.ravel()
-        y = sq.y0 + h * j.ravel()
-        coords.append((L, x, y))
+        x, y = node_coords(d, sq)
+        coords.append((np.arange(n * n), x, y))
     pairs = []
     tol = 1e-9
     for m in range(prob.q):
@@ -287,7 +312,7 @@ def assemble_replicated(prob):
     C = c_matrix(prob.E, prob.nu, prob.plane_strain)
     Ks, fs, ms = [], [], []
     for m, sq in enumerate(prob.subs):
-        K, M = assemble_square(d, sq.x0, sq.y0, sq.side, C)
+        K, M = assemble_square(d, sq.x0, sq.y0, sq.side, C, getattr(sq, "edges", None))
         f = body_load(d, M, prob.body)
         for tr in prob.tractions:
             if tr.sub == m:

@@ -191,3 +191,71 @@ def batch_energy_loss_grad(out: np.ndarray, targets, A, nrow, ranks):
         tot += l
         g[:, j] = gj / B
     return tot / B, g
+
+
+def batch_core_loss_grad(out: np.ndarray, targets):
+    """The plain loss on the packed cores, for targets brought to one gauge:
+    mean over the columns of ||o_j - u_j||^2 / ||u_j||^2 and its gradient
+    2 (o_j - u_j) / (B ||u_j||^2)."""
+    B = out.shape[1]
+    g = np.zeros_like(out)
+    tot = 0.0
+    for j in range(B):
+        u = flatten(targets[j])
+        uu = float(u @ u)
+        d = out[:, j] - u
+        tot += float(d @ d) / uu
+        g[:, j] = 2.0 * d / (uu * B)
+    return tot / B, g
+
+
+def align_gauge(x, ref):
+    """x with the gauge of ref (same modes and ranks): from the last bond to
+    the first, the orthogonal Q that minimises ||Q^T X_k - R_k||_F (over the
+    left rank index of core k, the rest of the core flattened) is the polar
+    factor U V^T of M = X_k R_k^T = U S V^T (orthogonal Procrustes,
+    Schoenemann 1966); core k becomes Q^T X_k and core k-1 becomes X_{k-1} Q,
+    which leaves the tensor unchanged.  A bond whose M has a singular value
+    below 1e-13 of its largest keeps Q = I."""
+    X = [c.copy() for c in x]
+    for k in range(len(X) - 1, 0, -1):
+        r = X[k].shape[0]
+        M = X[k].reshape(r, -1) @ ref[k].reshape(r, -1).T
+        U, s, Vt = np.linalg.svd(M)
+        if not s[0] > 0.0 or s[-1] <= 1e-13 * s[0]:
+            continue
+        Q = U @ Vt
+        X[k] = np.tensordot(Q.T, X[k], axes=(1, 0))
+        X[k - 1] = np.tensordot(X[k - 1], Q, axes=(2, 0))
+    return X
+
+
+def tt_angle_loss_grad(o: np.ndarray, u_cores, nrow, ranks, A=None):
+    """Scale-invariant loss L = 1 - <x, u>^2 / (<x, x> <u, u>) of x = TT(o)
+    in the Frobenius inner product, or in <v, w>_A = <v, A w> for a
+    symmetric positive definite QTT matrix A: the squared relative error of
+    the best multiple alpha x, alpha = <x, u> / <x, x>.  With the
+    environment gradients Gxx = d<x, x>/dX / 2 and Gxu = d<x, u>/dX,
+    dL/dX = 2 <x,u> / (<x,x> <u,u>) (<x,u> / <x,x> Gxx - Gxu)."""
+    from . import qtt as T
+    X = unflatten(o, nrow, ranks)
+    z = T.matvec(A, X) if A is not None else X
+    w = T.matvec(A, u_cores) if A is not None else u_cores
+    xx, xu, uu = T.dot(X, z), T.dot(X, w), T.dot(u_cores, w)
+    loss = 1.0 - xu * xu / (xx * uu)
+    gxx = _env_grad(_left_envs(X, z), _right_envs(X, z), z)
+    gxu = _env_grad(_left_envs(X, w), _right_envs(X, w), w)
+    c = 2.0 * xu / (xx * uu)
+    g = [c * (xu / xx * a - b) for a, b in zip(gxx, gxu)]
+    return loss, flatten(g)
+
+
+def batch_angle_loss_grad(out: np.ndarray, targets, nrow, ranks, A=None):
+    B = out.shape[1]
+    g = np.zeros_like(out)
+    tot = 0.0
+    for j in range(B):
+        l, gj = tt_angle_loss_grad(out[:, j], targets[j], nrow, ranks, A)
+        tot += l
+        g[:, j] = gj / B
+    return tot / B, g

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libqtt.so")
 
 QTT_F64, QTT_F32, QTT_BF16 = 0, 1, 2
 _DTYPES = {"f64": QTT_F64, "f32": QTT_F32, "bf16": QTT_BF16}
-_METHODS = {"cg": 0, "chebyshev": 1, "fcg": 2, "als": 3}
+_METHODS = {"cg": 0, "chebyshev": 1, "fcg": 2, "als": 3, "amen": 4}
 MAX_CORES = 40
 
 
@@ -31,12 +31,13 @@ class _TT(C.Structure):
 
 class _Square(C.Structure):
     _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("side", C.c_double),
-                ("fixed", (C.c_uint8 * 2) * 4)]
+                ("fixed", (C.c_uint8 * 2) * 4), ("edges", C.c_double * 4)]
 
 
 class _Traction(C.Structure):
     _fields_ = [("sub", C.c_int32), ("side", C.c_int32), ("comp", C.c_int32),
-                ("nmodes", C.c_int32), ("amp", C.POINTER(C.c_double))]
+                ("nmodes", C.c_int32), ("amp", C.POINTER(C.c_double)),
+                ("constant", C.c_double)]
 
 
 class _Problem(C.Structure):
@@ -58,7 +59,8 @@ class _SolveOpts(C.Structure):
 class _SolveReport(C.Structure):
     _fields_ = [("status", C.c_int32), ("outer", C.c_int32), ("inner", C.c_int32),
                 ("residual", C.c_double), ("residual_hist", C.c_double * 64),
-                ("max_rank", C.c_int32), ("criterion", C.c_double), ("lmax", C.c_double)]
+                ("max_rank", C.c_int32), ("criterion", C.c_double), ("lmax", C.c_double),
+                ("warm_start", C.c_int32), ("warm_energy", C.c_double)]
 
 
 class _SolveCase(C.Structure):
@@ -71,7 +73,7 @@ class _SolveCase(C.Structure):
 class _MLP(C.Structure):
     _fields_ = [("nlayers", C.c_int32), ("sizes", C.POINTER(C.c_int32)),
                 ("params", C.c_void_p), ("adam_m", C.c_void_p), ("adam_v", C.c_void_p),
-                ("step", C.c_int64)]
+                ("step", C.c_int64), ("gemm_dtype", C.c_int32), ("loss", C.c_int32)]
 
 
 class _MVRCase(C.Structure):
@@ -113,6 +115,16 @@ def load_library(path: str = LIB_PATH):
     L.qtt_matvec_round_workspace.argtypes = [P(_TT), P(_TT), C.c_int32, P(sz)]
     L.qtt_dot.argtypes = [P(_TT), P(_TT), P(C.c_double), vp, sz, vp]
     L.qtt_dot_noalloc.argtypes = [P(_TT), P(_TT), P(C.c_double), vp]
+    L.qtt_tt_combine.argtypes = [C.c_int32, P(C.c_double), P(P(_TT)), P(_TT), vp]
+    L.qtt_tt_align.argtypes = [P(_TT), P(_TT), vp]
+    L.qtt_tt_contract_last.argtypes = [P(_TT), vp, P(_TT), vp]
+    L.qtt_warmstart_fit.argtypes = [P(_MLP), vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_float,
+                                    C.c_float, C.c_uint64, C.c_int32, P(C.c_int32), P(C.c_int32),
+                                    P(_TT), P(C.c_double), vp, sz, vp]
+    L.qtt_warmstart_fit_workspace.argtypes = [P(_MLP), C.c_int32, C.c_int32, C.c_int32,
+                                              P(C.c_int32), P(C.c_int32), P(_TT), P(sz)]
+    L.qtt_warmstart_infer_tt.argtypes = [P(_MLP), vp, C.c_int32, P(C.c_int32), P(C.c_int32),
+                                         P(_TT), vp, sz, vp]
     L.qtt_kernel_timing.argtypes = [C.c_int32]
     L.qtt_kernel_timing_read.argtypes = [C.c_char_p, P(C.c_double), P(C.c_int64)]
     L.qtt_axpby.argtypes = [C.c_double, P(_TT), C.c_double, P(_TT), P(_TT), vp, sz, vp]
@@ -136,7 +148,8 @@ def load_library(path: str = LIB_PATH):
     L.qtt_autotune_batched.argtypes = [C.c_int32, P(_SolveCase), P(C.c_int32), P(C.c_double)]
     for name in ("qtt_matvec", "qtt_round", "qtt_round_workspace", "qtt_round_sketch",
                  "qtt_round_sketch_workspace", "qtt_matvec_round", "qtt_matvec_round_workspace",
-                 "qtt_dot", "qtt_dot_noalloc", "qtt_axpby", "qtt_kernel_timing",
+                 "qtt_dot", "qtt_dot_noalloc", "qtt_axpby", "qtt_kernel_timing", "qtt_tt_combine",
+                 "qtt_warmstart_fit", "qtt_warmstart_fit_workspace", "qtt_warmstart_infer_tt",
                  "qtt_kernel_timing_read",
                  "qtt_assemble_stiffness", "qtt_assemble_workspace", "qtt_assemble_bpx", "qtt_solve",
                  "qtt_solve_workspace", "qtt_solve_batched", "qtt_autotune_batched",
@@ -326,11 +339,36 @@ def dot(x: TT, y: TT) -> float:
     return out.value
 
 
-def dot_noalloc(x: TT, y: TT) -> float:
-    """qtt_dot_noalloc: <x, y> with the library's own device scratch."""
-    out = C.c_double()
-    _check(lib().qtt_dot_noalloc(C.byref(x.c), C.byref(y.c), C.byref(out), _stream_ptr()))
-    return out.value
+def tt_combine(coeffs, trains) -> "TT":
+    """qtt_tt_combine: sum_i coeffs[i] trains[i] (ranks add)."""
+    D = trains[0].D
+    ranks = [1] + [sum(t.ranks[k] for t in trains) for k in range(1, D)] + [1]
+    need = sum(ranks[k] * trains[0].nrow[k] * ranks[k + 1] for k in range(D))
+    z = TT(trains[0].nrow, None, [1] * (D + 1), need)
+    cs = (C.c_double * len(trains))(*[float(c) for c in coeffs])
+    ptrs = (C.POINTER(_TT) * len(trains))(*[C.pointer(t.c) for t in trains])
+    _check(lib().qtt_tt_combine(len(trains), cs, ptrs, C.byref(z.c), _stream_ptr()))
+    return z
+
+
+def tt_contract_last(x: "TT", w) -> "TT":
+    """qtt_tt_contract_last: x with its last (parameter) core contracted
+    against the weights w (a host sequence, copied to the device)."""
+    torch = _torch()
+    wd = torch.as_tensor(np.asarray(w, dtype=np.float64).reshape(-1), device="cuda")
+    D = x.D
+    need = sum(x.ranks[k] * x.nrow[k] * x.ranks[k + 1] for k in range(D - 2))
+    need += x.ranks[D - 2] * x.nrow[D - 2]
+    y = TT(x.nrow[:D - 1], None, [1] * D, need)
+    _check(lib().qtt_tt_contract_last(C.byref(x.c), C.c_void_p(wd.data_ptr()), C.byref(y.c),
+                                      _stream_ptr()))
+    y._keep = wd
+    return y
+
+
+def tt_align(x: "TT", ref: "TT") -> None:
+    """qtt_tt_align: x brought, in place, to the gauge of ref."""
+    _check(lib().qtt_tt_align(C.byref(x.c), C.byref(ref.c), _stream_ptr()))
 
 
 def kernel_timing(enable: bool) -> None:
@@ -343,6 +381,13 @@ def kernel_timing_read(kernel: str):
     ms, n = C.c_double(), C.c_int64()
     _check(lib().qtt_kernel_timing_read(kernel.encode(), C.byref(ms), C.byref(n)))
     return ms.value, n.value
+
+
+def dot_noalloc(x: TT, y: TT) -> float:
+    """qtt_dot_noalloc: <x, y> with the library's own device scratch."""
+    out = C.c_double()
+    _check(lib().qtt_dot_noalloc(C.byref(x.c), C.byref(y.c), C.byref(out), _stream_ptr()))
+    return out.value
 
 
 def axpby(a: float, x: TT, b: float, y: TT) -> TT:
@@ -374,6 +419,9 @@ def problem_from_workload(p, coupling: str = "symmetric") -> Problem:
         for a in range(4):
             for b in range(2):
                 subs[i].fixed[a][b] = 1 if s.fixed[a][b] else 0
+        edges = getattr(s, "edges", None)
+        for a in range(4):
+            subs[i].edges[a] = float(edges[a]) if edges is not None else 0.0
     keep = [subs]
     trs = (_Traction * max(len(p.tractions), 1))()
     for i, t in enumerate(p.tractions):
@@ -381,6 +429,7 @@ def problem_from_workload(p, coupling: str = "symmetric") -> Problem:
         keep.append(amp)
         trs[i].sub, trs[i].side, trs[i].comp, trs[i].nmodes = t.sub, t.side, t.comp, len(t.amp)
         trs[i].amp = amp
+        trs[i].constant = float(getattr(t, "constant", 0.0))
     keep.append(trs)
     c = _Problem(p.level, len(p.subs), subs, p.E, p.nu, 1 if p.plane_strain else 0,
                  (C.c_double * 2)(*p.body), len(p.tractions), trs,
@@ -475,13 +524,14 @@ def solve(K: TT, f: TT, opts: SolveOpts, x0: Optional[TT] = None, ws=None):
 def _report_dict(rep, opts):
     if opts.method == "cg":
         nh = rep.outer + 1
-    elif opts.method == "als":
+    elif opts.method in ("als", "amen"):
         nh = rep.outer            # energy decrease of each sweep
     else:
         nh = rep.inner // max(opts.check_every, 1) + 1
     return dict(status=rep.status, outer=rep.outer, inner=rep.inner, residual=rep.residual,
                 residual_hist=[rep.residual_hist[i] for i in range(min(nh, 64))],
-                max_rank=rep.max_rank, criterion=rep.criterion, lmax=rep.lmax)
+                max_rank=rep.max_rank, criterion=rep.criterion, lmax=rep.lmax,
+                warm_start=rep.warm_start, warm_energy=rep.warm_energy)
 
 
 class Batch:
@@ -597,9 +647,16 @@ def matvec_round_batched(batch: StepBatch):
 
 class MLP:
     """The warm-start network: FP32 parameters and Adam moments in device
-    memory (layout of qtt_mlp), initial values given by the caller."""
+    memory (layout of qtt_mlp), initial values given by the caller; gemm
+    "f32" or "bf16" (BF16 operands, FP32 accumulation on the matrix
+    cores); loss "tt" (gauge-invariant distance of the trains), "cores"
+    (distance of the packed cores, targets in one gauge) or "angle" (the
+    squared relative error of the best multiple of the train), settable
+    later through the attribute `loss`."""
 
-    def __init__(self, sizes, params):
+    _LOSSES = {"tt": 0, "cores": 1, "angle": 2}
+
+    def __init__(self, sizes, params, gemm: str = "f32", loss: str = "tt"):
         torch = _torch()
         self.sizes = [int(v) for v in sizes]
         self._sizes = (C.c_int32 * len(self.sizes))(*self.sizes)
@@ -611,7 +668,16 @@ class MLP:
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
         self.c = _MLP(len(self.sizes) - 1, self._sizes, self.params.data_ptr(),
-                      self.m.data_ptr(), self.v.data_ptr(), 0)
+                      self.m.data_ptr(), self.v.data_ptr(), 0, _DTYPES[gemm],
+                      self._LOSSES[loss])
+
+    @property
+    def loss(self) -> str:
+        return {v: k for k, v in self._LOSSES.items()}[self.c.loss]
+
+    @loss.setter
+    def loss(self, kind: str) -> None:
+        self.c.loss = self._LOSSES[kind]
 
     def infer(self, a):
         """a: (nin, B) array -> (nout, B) float32 tensor on the device."""
@@ -628,6 +694,45 @@ class MLP:
                                          C.c_void_p(_aligned_ptr(ws)), ws.numel() - 256,
                                          _stream_ptr()))
         return out.t()
+
+    def fit(self, a, targets, batch: int, epochs: int, lr: float, lr_final: float, seed: int,
+            nrow, ranks, metric: Optional["TT"] = None):
+        """qtt_warmstart_fit on device columns a (nin x n) and targets (nout x
+        n); returns the mean loss of each pass."""
+        mp = C.byref(metric.c) if metric is not None else None
+        n = a.shape[1]
+        D = len(nrow)
+        nr = (C.c_int32 * D)(*nrow)
+        rk = (C.c_int32 * (D + 1))(*ranks)
+        need = C.c_size_t()
+        _check(lib().qtt_warmstart_fit_workspace(C.byref(self.c), n, batch, D, nr, rk, mp,
+                                                 C.byref(need)))
+        ws = _workspace(need.value)
+        hist = (C.c_double * epochs)()
+        _check(lib().qtt_warmstart_fit(C.byref(self.c), C.c_void_p(a.data_ptr()),
+                                       C.c_void_p(targets.data_ptr()), n, batch, epochs,
+                                       float(lr), float(lr_final), int(seed), D, nr, rk, mp, hist,
+                                       C.c_void_p(_aligned_ptr(ws)), ws.numel() - 256,
+                                       _stream_ptr()))
+        return list(hist)
+
+    def infer_tt(self, a, nrow, ranks) -> "TT":
+        """qtt_warmstart_infer_tt: the warm-start train for one parameter
+        vector a (nin floats)."""
+        torch = _torch()
+        at = torch.as_tensor(np.asarray(a, dtype=np.float32).reshape(-1), device="cuda")
+        D = len(nrow)
+        nr = (C.c_int32 * D)(*nrow)
+        rk = (C.c_int32 * (D + 1))(*ranks)
+        x0 = TT(list(nrow), None, [1] * (D + 1), self.sizes[-1])
+        need = C.c_size_t()
+        _check(lib().qtt_warmstart_workspace(C.byref(self.c), 1, 0, None, None, None,
+                                             C.byref(need)))
+        ws = _workspace(need.value)
+        _check(lib().qtt_warmstart_infer_tt(C.byref(self.c), C.c_void_p(at.data_ptr()), D, nr, rk,
+                                            C.byref(x0.c), C.c_void_p(_aligned_ptr(ws)),
+                                            ws.numel() - 256, _stream_ptr()))
+        return x0
 
     def train_step(self, a, targets, nrow, ranks, lr: float, metric: Optional["TT"] = None) -> float:
         """a: (nin, B) and targets (nout, B) float32 device tensors with

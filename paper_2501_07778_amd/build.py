@@ -30,8 +30,9 @@ SOURCES = [
     "k_full.hip",
     "batched.cpp",
     "k_mlp.hip",
-    "ktimer.cpp",
     "noalloc.cpp",
+    "ktimer.cpp",
+    "combine.cpp",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -54,11 +54,24 @@ struct AlsLayout {
   double *dense = nullptr, *full_ws = nullptr;
   int64_t N = 0;
   int32_t *rk_in = nullptr;       // device ranks of the packed K, f, x0
+  double *start_ws = nullptr;     // energy of a start vector (<= caps)
+  int64_t start_elems = 0;
+  // AMEn enrichment: the rounded residual z, u + alpha z, their scratch
+  TTDesc Z, U2;
+  RoundWs rws;                    // rounding of f - K u after its sketch
+  double *sk_ws = nullptr;
+  double *en_ws = nullptr;
+  int64_t en_elems = 0;
 };
 
-// device scalars: energy, ||f||^2, residual, then per local solve of a
-// sweep the pair (||y - x_k||^2, ||y||^2)
-enum { A_YG = 0, A_FN2 = 2, A_RES = 4, A_LOC = 8 };
+// device scalars: energy, ||f||^2, residual, <x0, K x0> and <f, x0> of a
+// start vector, then per local solve of a sweep the pair
+// (||y - x_k||^2, ||y||^2)
+enum { A_YG = 0, A_FN2 = 2, A_RES = 4, A_X0KX0 = 6, A_FX0 = 7, A_LOC = 8 };
+// enrichment scalars after the per-solve pairs: <f, z> and <u, K z>
+// adjacent (the numerator of alpha), <z, K z>, alpha, <z, z>
+enum { A_ZF = A_LOC + 2 * (QTT_MAXD + 1), A_UKZ, A_ZKZ, A_ALPHA, A_ZZ, A_END };
+constexpr int ENRICH_OVERSAMPLE = 8;
 
 bool carve_als(Arena &ar, const qtt_tt *K, const qtt_tt *f, const qtt_solve_opts *o,
                AlsLayout &L) {
@@ -91,9 +104,22 @@ bool carve_als(Arena &ar, const qtt_tt *K, const qtt_tt *f, const qtt_solve_opts
   L.tmp = (double *)ar.take(sizeof(double) * nmax);
   L.Rq = (double *)ar.take(sizeof(double) * rmax * rmax);
   L.tau = (double *)ar.take(sizeof(double) * rmax);
-  L.sc = (double *)ar.take(sizeof(double) * (A_LOC + 2 * (D + 1)));
+  L.sc = (double *)ar.take(sizeof(double) * A_END);
   L.flag = (int *)ar.take(sizeof(int) * 4);
-  ok = round_ws_take(ar, L.U.v, L.rw) && ok;
+  if (o->method == QTT_SOLVE_AMEN) {
+    // u + alpha z: the iterate's ranks (<= rmax - rmax_in after every
+    // enrichment) plus the residual's (<= rmax_in), not limited by the
+    // mode products; its rounding workspace also serves the final one
+    const std::vector<int> cu = bounded_caps(D, n, nullptr, o->rmax - o->rmax_in);
+    const std::vector<int> cz = bounded_caps(D, n, nullptr, o->rmax_in);
+    std::vector<int> c2(D + 1, 1);
+    for (int k = 1; k < D; ++k) c2[k] = cu[k] + cz[k];
+    ok = arena_tt(ar, L.Z, D, n, nullptr, cz) && ok;
+    ok = arena_tt(ar, L.U2, D, n, nullptr, c2) && ok;
+    ok = round_ws_take(ar, L.U2.v, L.rw) && ok;
+  } else {
+    ok = round_ws_take(ar, L.U.v, L.rw) && ok;
+  }
   // residual: K u has ranks R_k c_k, f - K u has f's ranks added
   std::vector<int> pc(c), rc(c);
   for (int k = 0; k <= D; ++k) {
@@ -113,6 +139,26 @@ bool carve_als(Arena &ar, const qtt_tt *K, const qtt_tt *f, const qtt_solve_opts
   fw = std::max(fw, full_ws_elems(fv, fr.data()));
   L.full_ws = (double *)ar.take(sizeof(double) * fw);
   L.rk_in = (int32_t *)ar.take(sizeof(int32_t) * 3 * (QTT_MAXD + 1));
+  // <x0, K x0> and <f, x0> of a start vector with ranks up to the caps
+  {
+    TTView uv, kv, fv2;
+    layout(uv, D, n, nullptr, c);
+    layout(kv, D, n, K->ncol, std::vector<int>(K->ranks, K->ranks + D + 1));
+    layout(fv2, D, n, nullptr, std::vector<int>(f->ranks, f->ranks + D + 1));
+    L.start_elems = std::max(dot3_ws_elems(uv, kv, uv), dot_ws_elems(fv2, uv));
+    L.start_ws = (double *)ar.take(sizeof(double) * L.start_elems);
+  }
+  if (o->method == QTT_SOLVE_AMEN) {
+    ok = round_ws_take(ar, L.Rs.v, L.rws) && ok;
+    L.sk_ws = (double *)ar.take(sizeof(double) *
+                                sketch_ws_elems(L.Rs.v, o->rmax_in + ENRICH_OVERSAMPLE));
+    TTView kv, fv2;
+    layout(kv, D, n, K->ncol, std::vector<int>(K->ranks, K->ranks + D + 1));
+    layout(fv2, D, n, nullptr, std::vector<int>(f->ranks, f->ranks + D + 1));
+    L.en_elems = std::max({dot3_ws_elems(L.U.v, kv, L.Z.v), dot3_ws_elems(L.Z.v, kv, L.Z.v),
+                           dot_ws_elems(fv2, L.Z.v), dot_ws_elems(L.Z.v, L.Z.v)});
+    L.en_ws = (double *)ar.take(sizeof(double) * L.en_elems);
+  }
   return ok && ar.ok();
 }
 
@@ -140,6 +186,9 @@ void view_of_packed(const qtt_tt *t, TTView &v, int32_t *rk_dev) {
 
 qtt_status check_als_opts(const qtt_solve_opts *o) {
   if (!(o->tol > 0.0) || !(o->eps >= 0.0)) return fail(QTT_E_INVAL, "ALS: tol > 0, eps >= 0");
+  if (o->method == QTT_SOLVE_AMEN &&
+      (o->rmax_in < 1 || o->rmax < 2 * o->rmax_in || !(o->eps_in >= 0.0)))
+    return fail(QTT_E_INVAL, "AMEN: rmax_in >= 1, rmax >= 2 rmax_in and eps_in >= 0 required");
   if (o->rmax < 1 || o->rmax > 512) return fail(QTT_E_INVAL, "ALS: rmax must be in 1..512");
   if (o->maxit_out < 1) return fail(QTT_E_INVAL, "ALS: maxit_out (sweeps) must be >= 1");
   if (o->compute != QTT_F64)
@@ -155,9 +204,10 @@ size_t als_workspace_bytes(const qtt_tt *K, const qtt_tt *f, const qtt_solve_opt
   return ar.used + 4096;
 }
 
-qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
+qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *xin,
                      const qtt_solve_opts *o, qtt_tt *u, qtt_solve_report *rep, void *ws,
                      size_t ws_bytes, hipStream_t s) {
+  const qtt_tt *x0 = xin;
   Arena ar;
   ar.base = (char *)ws;
   ar.size = ws_bytes;
@@ -167,10 +217,13 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
   const int32_t *n = K->nrow;
   // rank ramp: stages at rmax_in, 2 rmax_in, ... then rmax (cheap sweeps at
   // low rank find the subspace; the local solves cost O((r n r)^3))
+  const bool amen = o->method == QTT_SOLVE_AMEN;
   std::vector<int> stage_r;
-  if (o->rmax_in > 0 && o->rmax_in < o->rmax)
+  if (amen)
+    stage_r.push_back(o->rmax_in);   // start ranks; the enrichment sets the rest
+  else if (o->rmax_in > 0 && o->rmax_in < o->rmax)
     for (int r = o->rmax_in; r < o->rmax; r *= 2) stage_r.push_back(r);
-  stage_r.push_back(o->rmax);
+  if (!amen) stage_r.push_back(o->rmax);
   // a stage whose caps (limited by the mode products) equal the next one's
   // is not a lower rank: drop it
   for (size_t i = 0; i + 1 < stage_r.size();) {
@@ -180,7 +233,13 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
       ++i;
   }
   size_t st0 = 0;
-  if (x0)  // start at the first stage whose caps hold x0
+  if (amen && x0) {
+    const std::vector<int> cs = bounded_caps(D, n, nullptr, o->rmax - o->rmax_in);
+    for (int k = 0; k <= D; ++k)
+      if (x0->ranks[k] > cs[k])
+        return fail(QTT_E_SHAPE, "AMEN: x0 ranks must be <= rmax - rmax_in");
+  }
+  if (x0 && !amen)  // start at the first stage whose caps hold x0
     while (st0 + 1 < stage_r.size()) {
       const std::vector<int> cs = bounded_caps(D, n, nullptr, stage_r[st0]);
       bool fits = true;
@@ -189,6 +248,7 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
       ++st0;
     }
   std::vector<int> c = bounded_caps(D, n, nullptr, stage_r[st0]);
+  if (amen && x0) c.assign(x0->ranks, x0->ranks + D + 1);
   const int32_t *RK = K->ranks, *RF = f->ranks;
   const std::vector<int64_t> koff = packed_offsets(K), foff = packed_offsets(f);
   auto core = [&](int k) { return L.U.v.data + L.U.v.off[k]; };
@@ -208,6 +268,36 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
   QTT_HIP(tt_full(fv, f->ranks, L.dense, L.full_ws, s));
   QTT_HIP(launch_diff_norm2(L.dense, nullptr, L.N, L.sc + A_FN2, s));
 
+  // the view of K for products and three-operand inner products
+  TTView Kv;
+  view_of_packed(K, Kv, L.rk_in + (QTT_MAXD + 1));
+  QTT_HIP(upload_ranks(Kv, K->ranks, s));
+
+  // A start vector enters scaled by alpha = <f, x0> / <x0, K x0>, the
+  // minimiser of the energy J(alpha x0) = alpha^2 <x0, K x0> / 2 -
+  // alpha <f, x0>, whose value -<f, x0>^2 / (2 <x0, K x0>) is below J(0) = 0
+  // unless x0 has no component along the solution (<f, x0> = 0) or its
+  // values are not finite: then the solve falls back to its cold start.
+  double x0_energy = 0.0, x0_alpha = 1.0;
+  if (x0) {
+    TTView xv;
+    view_of_packed(x0, xv, L.rk_in + 2 * (QTT_MAXD + 1));
+    QTT_HIP(upload_ranks(xv, x0->ranks, s));
+    QTT_HIP(launch_dot3(xv, Kv, xv, L.sc + A_X0KX0, L.start_ws, L.start_elems, s));
+    QTT_HIP(launch_dot(fv, xv, L.sc + A_FX0, L.start_ws, L.start_elems, s));
+    double e2[2];
+    QTT_HIP(hipMemcpyAsync(e2, L.sc + A_X0KX0, sizeof(e2), hipMemcpyDeviceToHost, s));
+    QTT_HIP(hipStreamSynchronize(s));
+    const double xkx = e2[0], fx = e2[1];
+    x0_alpha = fx / xkx;
+    x0_energy = -0.5 * fx * fx / xkx;
+    if (!(xkx > 0.0) || !std::isfinite(x0_alpha) || !(x0_energy < 0.0)) {
+      x0 = nullptr;
+      st0 = 0;
+      c = bounded_caps(D, n, nullptr, stage_r[0]);
+    }
+  }
+  const int warm = xin ? (x0 ? 1 : -1) : 0;
   // start: x0 zero-padded to the caps, else deterministic random cores
   if (x0) {
     const std::vector<int64_t> xoff = packed_offsets(x0);
@@ -221,6 +311,7 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
     std::vector<int32_t> c32(c.begin(), c.end());
     QTT_HIP(upload_ranks(L.U.v, c32.data(), s));
   }
+  if (x0) QTT_HIP(launch_scale(L.U.v, x0_alpha, s));
   QTT_HIP(hipMemsetAsync(L.flag, 0, sizeof(int), s));
 
   // orthogonality-centre moves
@@ -299,62 +390,131 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
   qtt_status st;
   bool converged = false;
   constexpr int RAMP_SWEEPS = 3;
-  for (size_t stg = st0; stg < stage_r.size() && !converged && sweep < o->maxit_out; ++stg) {
-    const bool last = stg + 1 == stage_r.size();
-    if (stg > st0) {
-      // zero-pad every core to the next stage's caps (through the scratch)
-      const std::vector<int> cn = bounded_caps(D, n, nullptr, stage_r[stg]);
-      for (int k = 0; k < D; ++k) {
-        QTT_HIP(hipMemcpyAsync(L.tmp, core(k), sizeof(double) * csize(k),
-                               hipMemcpyDeviceToDevice, s));
-        QTT_HIP(als_pad_core(L.tmp, c[k], n[k], c[k + 1], core(k), cn[k], cn[k + 1], s));
-      }
-      c = cn;
-      std::vector<int32_t> c32(c.begin(), c.end());
-      QTT_HIP(upload_ranks(L.U.v, c32.data(), s));
-    }
-    // right-orthogonalise cores D-1..1, the environments from the right,
-    // then the first core
+  double unorm = 0.0;
+  // right-orthogonalise cores D-1..1, the environments from the right, then
+  // solve the first core
+  auto restart = [&]() -> qtt_status {
     for (int k = D - 1; k >= 1; --k) QTT_HIP(lq_step(k));
     for (int k = D - 1; k >= 1; --k) QTT_HIP(env_right(k));
     QTT_HIP(solve_core(0, 0));
-    if ((st = read_energy(J, flag)) != QTT_OK) return st;
+    qtt_status e = read_energy(J, flag);
+    if (e != QTT_OK) return e;
     if (flag) return fail(QTT_E_INVAL, "ALS: local matrix not positive definite (is K SPD?)");
-    if (D == 1) {
-      converged = true;
-      break;
-    }
-    const int budget = last ? o->maxit_out - sweep : std::min(RAMP_SWEEPS, o->maxit_out - sweep);
-    for (int sw = 0; sw < budget && !converged; ++sw, ++sweep) {
-      if (sw % 2 == 0) {
-        for (int k = 0; k + 1 < D; ++k) {
-          QTT_HIP(qr_step(k));
-          QTT_HIP(env_left(k));
-          QTT_HIP(solve_core(k + 1, k));
-        }
-      } else {
-        for (int k = D - 1; k >= 1; --k) {
-          QTT_HIP(lq_step(k));
-          QTT_HIP(env_right(k));
-          QTT_HIP(solve_core(k - 1, D - 1 - k));
-        }
+    return QTT_OK;
+  };
+  // one sweep (forward on even, backward on odd counts); crit = the change
+  // of u over the sweep relative to ||u||
+  auto sweep_once = [&](bool forward, int rank_label) -> qtt_status {
+    if (forward) {
+      for (int k = 0; k + 1 < D; ++k) {
+        QTT_HIP(qr_step(k));
+        QTT_HIP(env_left(k));
+        QTT_HIP(solve_core(k + 1, k));
       }
-      // change of u over the sweep: sum of the local changes over ||u||
-      std::vector<double> loc(2 * (D - 1));
-      QTT_HIP(hipMemcpyAsync(loc.data(), L.sc + A_LOC, sizeof(double) * 2 * (D - 1),
-                             hipMemcpyDeviceToHost, s));
-      if ((st = read_energy(J, flag)) != QTT_OK) return st;
-      if (flag) return fail(QTT_E_INVAL, "ALS: local matrix not positive definite (is K SPD?)");
-      double dsum = 0.0;
-      for (int j = 0; j < D - 1; ++j) dsum += std::sqrt(std::max(loc[2 * j], 0.0));
-      const double unorm = std::sqrt(std::max(loc[2 * (D - 2) + 1], 0.0));
-      if (!std::isfinite(J) || !std::isfinite(dsum)) return fail(QTT_E_NOCONV, "ALS: not finite");
-      crit = unorm > 0.0 ? dsum / unorm : 0.0;
-      if (sweep < 64) R.residual_hist[sweep] = crit;
+    } else {
+      for (int k = D - 1; k >= 1; --k) {
+        QTT_HIP(lq_step(k));
+        QTT_HIP(env_right(k));
+        QTT_HIP(solve_core(k - 1, D - 1 - k));
+      }
+    }
+    // change of u over the sweep: sum of the local changes over ||u||
+    std::vector<double> loc(2 * (D - 1));
+    QTT_HIP(hipMemcpyAsync(loc.data(), L.sc + A_LOC, sizeof(double) * 2 * (D - 1),
+                           hipMemcpyDeviceToHost, s));
+    qtt_status e = read_energy(J, flag);
+    if (e != QTT_OK) return e;
+    if (flag) return fail(QTT_E_INVAL, "ALS: local matrix not positive definite (is K SPD?)");
+    double dsum = 0.0;
+    for (int j = 0; j < D - 1; ++j) dsum += std::sqrt(std::max(loc[2 * j], 0.0));
+    unorm = std::sqrt(std::max(loc[2 * (D - 2) + 1], 0.0));
+    if (!std::isfinite(J) || !std::isfinite(dsum)) return fail(QTT_E_NOCONV, "ALS: not finite");
+    crit = unorm > 0.0 ? dsum / unorm : 0.0;
+    if (sweep < 64) R.residual_hist[sweep] = crit;
+    if (trace)
+      std::fprintf(stderr, "[qtt_solve als] %.3fs rank %d sweep %d energy %.15e change %.3e\n",
+                   secs(), rank_label, sweep, J, crit);
+    return QTT_OK;
+  };
+  if (D == 1) {
+    if ((st = restart()) != QTT_OK) return st;
+    converged = true;
+  } else if (amen) {
+    // residual enrichment: z = round(f - K u, eps_in, rmax_in) by a sketch,
+    // alpha = <f - K u, z> / <z, K z>, then u <- round(u + alpha z, eps,
+    // rmax - rmax_in); echange = |alpha| ||z|| / ||u||
+    uint64_t call = 0;
+    double echange = HUGE_VAL;
+    auto residual_direction = [&]() -> qtt_status {
+      QTT_HIP(launch_matvec(Kv, L.U.v, L.Ku.v, QTT_F64, s));
+      QTT_HIP(launch_axpby(1.0, nullptr, fv, -1.0, nullptr, L.Ku.v, L.Rs.v, s));
+      const int ell = o->rmax_in + ENRICH_OVERSAMPLE;
+      QTT_HIP(sketch_tt(L.Rs.v, ell, o->seed, call++, L.sk_ws, s));
+      QTT_HIP(round_tt(L.Rs.v, o->eps_in, o->rmax_in, L.rws, s, true, ell));
+      QTT_HIP(launch_copy_tt(L.Rs.v, L.Z.v, s));
+      QTT_HIP(launch_dot(fv, L.Z.v, L.sc + A_ZF, L.en_ws, L.en_elems, s));
+      QTT_HIP(launch_dot3(L.U.v, Kv, L.Z.v, L.sc + A_UKZ, L.en_ws, L.en_elems, s));
+      QTT_HIP(launch_dot3(L.Z.v, Kv, L.Z.v, L.sc + A_ZKZ, L.en_ws, L.en_elems, s));
+      QTT_HIP(launch_dot(L.Z.v, L.Z.v, L.sc + A_ZZ, L.en_ws, L.en_elems, s));
+      QTT_HIP(launch_scalar(SC_DIFF_DIV, L.sc + A_ALPHA, L.sc + A_ZF, L.sc + A_ZKZ, 0.0, s));
+      double v[A_END - A_ZF];
+      QTT_HIP(hipMemcpyAsync(v, L.sc + A_ZF, sizeof(v), hipMemcpyDeviceToHost, s));
+      QTT_HIP(hipStreamSynchronize(s));
+      const double alpha = v[A_ALPHA - A_ZF], zz = v[A_ZZ - A_ZF];
+      if (!std::isfinite(alpha) || !std::isfinite(zz))
+        return fail(QTT_E_NOCONV, "AMEN: enrichment not finite");
+      echange = unorm > 0.0 ? std::fabs(alpha) * std::sqrt(std::max(zz, 0.0)) / unorm : 0.0;
+      return QTT_OK;
+    };
+    auto enrich = [&]() -> qtt_status {
+      QTT_HIP(launch_axpby(1.0, nullptr, L.U.v, 1.0, L.sc + A_ALPHA, L.Z.v, L.U2.v, s));
+      QTT_HIP(round_tt(L.U2.v, o->eps, o->rmax - o->rmax_in, L.rw, s));
+      int32_t r2[QTT_MAXD + 1];
+      QTT_HIP(hipMemcpyAsync(r2, L.U2.v.rk, sizeof(int32_t) * (D + 1), hipMemcpyDeviceToHost, s));
+      QTT_HIP(hipStreamSynchronize(s));
+      QTT_HIP(launch_copy_tt(L.U2.v, L.U.v, s));
+      for (int k = 0; k <= D; ++k) c[k] = r2[k];
+      return QTT_OK;
+    };
+    int maxr = 0;
+    while (!converged && sweep < o->maxit_out) {
+      maxr = *std::max_element(c.begin(), c.end());
+      if ((st = restart()) != QTT_OK) return st;
+      for (int sw = 0; sw < 2 && sweep < o->maxit_out; ++sw, ++sweep)
+        if ((st = sweep_once(sw % 2 == 0, maxr)) != QTT_OK) return st;
+      if ((st = residual_direction()) != QTT_OK) return st;
       if (trace)
-        std::fprintf(stderr, "[qtt_solve als] %.3fs rank %d sweep %d energy %.15e change %.3e\n",
-                     secs(), stage_r[stg], sweep, J, crit);
-      if (last && crit <= o->tol) converged = true;
+        std::fprintf(stderr, "[qtt_solve amen] %.3fs ranks up to %d, enrichment change %.3e\n",
+                     secs(), maxr, echange);
+      if (crit <= o->tol && echange <= o->tol) {
+        converged = true;
+        break;
+      }
+      if (sweep >= o->maxit_out) break;
+      if ((st = enrich()) != QTT_OK) return st;
+    }
+  } else {
+    for (size_t stg = st0; stg < stage_r.size() && !converged && sweep < o->maxit_out; ++stg) {
+      const bool last = stg + 1 == stage_r.size();
+      if (stg > st0) {
+        // zero-pad every core to the next stage's caps (through the scratch)
+        const std::vector<int> cn = bounded_caps(D, n, nullptr, stage_r[stg]);
+        for (int k = 0; k < D; ++k) {
+          QTT_HIP(hipMemcpyAsync(L.tmp, core(k), sizeof(double) * csize(k),
+                                 hipMemcpyDeviceToDevice, s));
+          QTT_HIP(als_pad_core(L.tmp, c[k], n[k], c[k + 1], core(k), cn[k], cn[k + 1], s));
+        }
+        c = cn;
+        std::vector<int32_t> c32(c.begin(), c.end());
+        QTT_HIP(upload_ranks(L.U.v, c32.data(), s));
+      }
+      if ((st = restart()) != QTT_OK) return st;
+      const int budget =
+          last ? o->maxit_out - sweep : std::min(RAMP_SWEEPS, o->maxit_out - sweep);
+      for (int sw = 0; sw < budget && !converged; ++sw, ++sweep) {
+        if ((st = sweep_once(sw % 2 == 0, stage_r[stg])) != QTT_OK) return st;
+        if (last && crit <= o->tol) converged = true;
+      }
     }
   }
   R.outer = sweep;
@@ -368,9 +528,6 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
   QTT_HIP(hipStreamSynchronize(s));
 
   // FP64 check: ||f - K u|| from the exact dense contraction of f - K u
-  TTView Kv;
-  view_of_packed(K, Kv, L.rk_in + (QTT_MAXD + 1));
-  QTT_HIP(upload_ranks(Kv, K->ranks, s));
   QTT_HIP(launch_matvec(Kv, L.U.v, L.Ku.v, QTT_F64, s));
   QTT_HIP(launch_axpby(1.0, nullptr, fv, -1.0, nullptr, L.Ku.v, L.Rs.v, s));
   std::vector<int32_t> rr(D + 1);
@@ -400,6 +557,8 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *x0,
   }
   R.max_rank = mr;
   R.status = converged ? QTT_OK : QTT_E_NOCONV;
+  R.warm_start = warm;
+  R.warm_energy = xin ? x0_energy : 0.0;
   if (rep) *rep = R;
   if (!converged) return fail(QTT_E_NOCONV, "ALS: change of u above tol after maxit_out sweeps");
   return QTT_OK;

@@ -471,22 +471,66 @@ void one_d(int d, double h, Rounder &rd, HTT &S1, HTT &M1, HTT &G1) {
   rd(G1);
 }
 
-// K_bd = sum_{c,c'} E_cc' (x) I_q (x) K_cc'
+// Edge vectors a, b of subdomain m: the map (s, t) -> x0 + s a + t b of the
+// parameter square (a square of side L: a = (L, 0), b = (0, L)).
+void edge_vectors(const qtt_square &q, double a[2], double b[2]) {
+  const bool given = q.edges[0] != 0.0 || q.edges[1] != 0.0 || q.edges[2] != 0.0 ||
+                     q.edges[3] != 0.0;
+  a[0] = given ? q.edges[0] : q.side;
+  a[1] = given ? q.edges[1] : 0.0;
+  b[0] = given ? q.edges[2] : 0.0;
+  b[1] = given ? q.edges[3] : q.side;
+}
+
+// K_bd = sum_{c,c'} E_cc' (x) I_q (x) K_cc'.  With the affine map A = [a b]
+// of the parameter square every element has the Jacobian A / (n - 1), and
+// the gradient is grad_x = A^-T grad_(s,t) (Sec. 3.4, exact here: the
+// Jacobian is constant).  So K_cc' = |det A| sum_{alpha,beta in {s,t}}
+// W_cc'[alpha][beta] S_alpha,beta with W_cc'[al][be] = sum_{p,q}
+// C(c,p,c',q) G[p][al] G[q][be], G = A^-T, C the elasticity tensor (test
+// component c and derivative p, trial c' and q), and the parameter-domain
+// Kronecker factors (1-D matrices at h = 1, their h cancels in 2-D; t
+// factor (x) s factor): S_ss = M1 (x) S1, S_tt = S1 (x) M1, S_st (test
+// derivative in s, trial in t) = G1^T (x) G1, S_ts = G1 (x) G1^T.  For the
+// square (G = I / L) this reduces to K_xx = C11 M1(x)S1 + C33 S1(x)M1 and
+// K_xy = C12 G1^T(x)G1 + C33 G1(x)G1^T.
 HTT block_stiffness(const Geometry &g, Rounder &rd) {
   double c11, c12, c22, c33;
   voigt(g.p, c11, c12, c22, c33);
+  // C(c, p, c', q), indices 0 = x, 1 = y
+  double Ct[2][2][2][2] = {};
+  Ct[0][0][0][0] = c11;
+  Ct[1][1][1][1] = c22;
+  Ct[0][0][1][1] = Ct[1][1][0][0] = c12;
+  Ct[0][1][0][1] = Ct[0][1][1][0] = Ct[1][0][0][1] = Ct[1][0][1][0] = c33;
+  double a[2], b[2];
+  edge_vectors(g.p->sub[0], a, b);
+  const double det = a[0] * b[1] - a[1] * b[0];
+  // G = A^-T with A = [a b] (columns): A^-1 = [[b1, -b0], [-a1, a0]] / det
+  const double G[2][2] = {{b[1] / det, -a[1] / det}, {-b[0] / det, a[0] / det}};
   HTT S1, M1, G1;
   one_d(g.d, 1.0, rd, S1, M1, G1);
   HTT G1t = transpose(G1);
-  HTT a = zkron(M1, S1), b = zkron(S1, M1), c = zkron(G1t, G1), e = zkron(G1, G1t);
-  HTT Kxx = add({&a, &b}, {c11, c33});
-  HTT Kyy = add({&b, &a}, {c22, c33});
-  HTT Kxy = add({&c, &e}, {c12, c33});
-  HTT Kyx = add({&e, &c}, {c12, c33});
-  rd(Kxx);
-  rd(Kyy);
-  rd(Kxy);
-  rd(Kyx);
+  HTT Sst[2][2] = {{zkron(M1, S1), zkron(G1t, G1)}, {zkron(G1, G1t), zkron(S1, M1)}};
+  HTT Kc[2][2];
+  for (int c = 0; c < 2; ++c)
+    for (int cp = 0; cp < 2; ++cp) {
+      std::vector<const HTT *> terms;
+      std::vector<double> coef;
+      for (int al = 0; al < 2; ++al)
+        for (int be = 0; be < 2; ++be) {
+          double w = 0.0;
+          for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 2; ++q) w += Ct[c][p][cp][q] * G[p][al] * G[q][be];
+          w *= std::fabs(det);
+          if (w == 0.0) continue;
+          terms.push_back(&Sst[al][be]);
+          coef.push_back(w);
+        }
+      Kc[c][cp] = add(terms, coef);
+      rd(Kc[c][cp]);
+    }
+  HTT &Kxx = Kc[0][0], &Kxy = Kc[0][1], &Kyx = Kc[1][0], &Kyy = Kc[1][1];
   HTT t00 = with_prefix_matrix(g, sel_matrix(2, 0, 0), eye(g.q), Kxx);
   HTT t01 = with_prefix_matrix(g, sel_matrix(2, 0, 1), eye(g.q), Kxy);
   HTT t10 = with_prefix_matrix(g, sel_matrix(2, 1, 0), eye(g.q), Kyx);
@@ -540,16 +584,21 @@ HTT load_vector(const Geometry &g, Rounder &rd, bool &any) {
   const int d = g.d, n = 1 << d;
   std::vector<HTT> terms;
   for (int m = 0; m < g.q; ++m) {
-    const double h = g.p->sub[m].side / (n - 1);
+    // parameter-domain 1-D mass (h = 1/(n-1)); the area element is |det A|
+    // and an edge's length element |a| (south, north) or |b| (west, east)
+    double a[2], b[2];
+    edge_vectors(g.p->sub[m], a, b);
+    const double det = std::fabs(a[0] * b[1] - a[1] * b[0]);
+    const double la = std::hypot(a[0], a[1]), lb = std::hypot(b[0], b[1]);
     HTT S1, M1, G1;
-    one_d(d, h, rd, S1, M1, G1);
+    one_d(d, 1.0 / (n - 1), rd, S1, M1, G1);
     for (int c = 0; c < 2; ++c) {
       if (g.p->body[c] == 0.0) continue;
       HTT mv = matvec_h(M1, ones1(d));
       rd(mv);
       HTT node = zkron(mv, mv);
       HTT t = with_prefix_vector(g, unit_vec(2, c), unit_vec(g.q, m), node);
-      for (auto &v : t.c[0]) v *= g.p->body[c];
+      for (auto &v : t.c[0]) v *= g.p->body[c] * det;
       terms.push_back(t);
     }
     for (int u = 0; u < g.p->ntrac; ++u) {
@@ -557,6 +606,10 @@ HTT load_vector(const Geometry &g, Rounder &rd, bool &any) {
       if (tr.sub != m) continue;
       std::vector<HTT> sines;
       std::vector<double> co;
+      if (tr.constant != 0.0) {
+        sines.push_back(ones1(d));
+        co.push_back(tr.constant);
+      }
       for (int k = 1; k <= tr.nmodes; ++k) {
         if (tr.amp[k - 1] == 0.0) continue;
         sines.push_back(sine1(d, k * M_PI / (n - 1)));
@@ -569,6 +622,7 @@ HTT load_vector(const Geometry &g, Rounder &rd, bool &any) {
       rd(tbar);
       HTT edge = matvec_h(M1, tbar);
       rd(edge);
+      for (auto &v : edge.c[0]) v *= (tr.side <= 1) ? lb : la;
       HTT node = (tr.side <= 1) ? zkron(edge, unit1(d, tr.side)) : zkron(unit1(d, tr.side - 2), edge);
       terms.push_back(with_prefix_vector(g, unit_vec(2, tr.comp), unit_vec(g.q, m), node));
     }
@@ -719,7 +773,7 @@ int64_t packed_size(const HTT &t) {
 qtt_status check_problem(const qtt_problem *p) {
   if (!p) return fail(QTT_E_INVAL, "problem is NULL");
   if (p->level < 1 || p->level > 19) return fail(QTT_E_INVAL, "level must be in 1..19");
-  if (p->q < 1 || p->q > 8) return fail(QTT_E_INVAL, "q must be in 1..8");
+  if (p->q < 1 || p->q > 32) return fail(QTT_E_INVAL, "q must be in 1..32");
   if (1 + (p->q > 1) + 2 * p->level > QTT_MAX_CORES) return fail(QTT_E_INVAL, "too many cores");
   if (!p->sub) return fail(QTT_E_INVAL, "sub is NULL");
   if (!(p->E > 0.0) || !(p->nu > -1.0 && p->nu < 0.5)) return fail(QTT_E_INVAL, "bad material");
@@ -728,6 +782,15 @@ qtt_status check_problem(const qtt_problem *p) {
   for (int m = 1; m < p->q; ++m)
     if (std::fabs(p->sub[m].side - p->sub[0].side) > 1e-12 * p->sub[0].side)
       return fail(QTT_E_UNSUPPORTED, "subdomains must share one side length");
+  for (int m = 0; m < p->q; ++m) {
+    const double *e = p->sub[m].edges;
+    if (e[0] == 0.0 && e[1] == 0.0 && e[2] == 0.0 && e[3] == 0.0) continue;
+    if (p->q > 1)
+      return fail(QTT_E_UNSUPPORTED, "parallelogram subdomains: one subdomain only (q = 1)");
+    const double det = e[0] * e[3] - e[1] * e[2];
+    if (!(std::fabs(det) > 1e-12 * (std::fabs(e[0] * e[3]) + std::fabs(e[1] * e[2]))))
+      return fail(QTT_E_INVAL, "degenerate parallelogram (edge vectors parallel)");
+  }
   if (p->ntrac < 0 || (p->ntrac > 0 && !p->trac)) return fail(QTT_E_INVAL, "bad tractions");
   for (int u = 0; u < p->ntrac; ++u) {
     const qtt_traction &t = p->trac[u];
@@ -994,6 +1057,9 @@ extern "C" qtt_status qtt_assemble_bpx(const qtt_problem *p, double eps, qtt_tt 
   qtt_status st = check_problem(p);
   if (st != QTT_OK) return st;
   if (p->q != 1) return fail(QTT_E_UNSUPPORTED, "the BPX preconditioner is built for q = 1");
+  if (p->sub[0].edges[0] != 0.0 || p->sub[0].edges[1] != 0.0 || p->sub[0].edges[2] != 0.0 ||
+      p->sub[0].edges[3] != 0.0)
+    return fail(QTT_E_UNSUPPORTED, "the BPX preconditioner is built for a square subdomain");
   if (!C || !C->data || !C->ranks || !C->ncol) return fail(QTT_E_INVAL, "C has a NULL field");
   const int D = 1 + 2 * p->level;
   if (C->ncores != D) return fail(QTT_E_SHAPE, "C needs ncores = 1 + 2 level");

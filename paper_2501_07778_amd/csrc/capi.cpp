@@ -67,7 +67,7 @@ qtt_status check_tt(const qtt_tt *t, const char *name, bool need_ranks) {
   if (!t->nrow || !t->ranks)
     return fail(QTT_E_INVAL, std::string(name) + ": NULL nrow or ranks");
   for (int k = 0; k < t->ncores; ++k) {
-    if (t->nrow[k] < 1 || t->nrow[k] > 64 || (t->ncol && (t->ncol[k] < 1 || t->ncol[k] > 8)))
+    if (t->nrow[k] < 1 || t->nrow[k] > 64 || (t->ncol && (t->ncol[k] < 1 || t->ncol[k] > 64)))
       return fail(QTT_E_INVAL, std::string(name) + ": mode out of range");
   }
   if (need_ranks) {
@@ -144,7 +144,6 @@ qtt_status qtt_matvec(const qtt_tt *A, const qtt_tt *x, qtt_tt *y,
   for (int k = 0; k < A->ncores; ++k) {
     if (A->ncol[k] != x->nrow[k]) return fail(QTT_E_SHAPE, "A column mode != x mode");
     if (y->nrow[k] != A->nrow[k]) return fail(QTT_E_SHAPE, "y mode != A row mode");
-    if (A->ncol[k] > 8) return fail(QTT_E_UNSUPPORTED, "column mode > 8");
   }
   if (compute != QTT_F64 && compute != QTT_F32 && compute != QTT_BF16)
     return fail(QTT_E_INVAL, "bad compute dtype");
@@ -296,7 +295,6 @@ static qtt_status check_matvec_args(const qtt_tt *A, const qtt_tt *x, qtt_dtype 
   if (A->ncores != x->ncores) return fail(QTT_E_SHAPE, "core counts differ");
   for (int k = 0; k < A->ncores; ++k) {
     if (A->ncol[k] != x->nrow[k]) return fail(QTT_E_SHAPE, "A column mode != x mode");
-    if (A->ncol[k] > 8) return fail(QTT_E_UNSUPPORTED, "column mode > 8");
   }
   if (compute != QTT_F64 && compute != QTT_F32 && compute != QTT_BF16)
     return fail(QTT_E_INVAL, "bad compute dtype");

@@ -1,6 +1,7 @@
 // k_mlp.hip — learned warm start: an MLP from load parameters to the QTT
 // cores of the displacement, trained on the GPU with a gauge-invariant loss
-// in TT space (Frobenius, or the energy norm of the stiffness matrix), gfx950.
+// in TT space (Frobenius, or the energy norm of the stiffness matrix) or a
+// plain loss on the cores of targets brought to one gauge, gfx950.
 //
 // Layout: column-major, one sample per column.  Layer l has W_l (out x in)
 // and b_l (out); hidden layers use ReLU, the output layer is linear.  The
@@ -76,6 +77,92 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// ------------------------------------------------------------ BF16 MFMA
+// C (M x N) = op(A) op(B) (+ bias per row) (ReLU) with the operands rounded
+// to BF16 (round to nearest even) as they are staged in LDS and FP32
+// accumulation in v_mfma_f32_16x16x32_bf16; FP32 in and out, column-major
+// like k_gemm32.  A 256-thread block computes a 64 x 64 tile; each of its
+// four wavefronts a 32 x 32 quarter as 2 x 2 MFMA tiles of 16 x 16, K in
+// steps of 32.  Operand layout of the instruction: lane l supplies row
+// (A) or column (B) l % 16 and eight K positions chosen by l / 16; both
+// operands use the same positions, so any such assignment sums over all
+// 32; the result: lane l holds rows 4 (l / 16) + v, v = 0..3, of column
+// l % 16.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+constexpr int BT = 64, BK = 32, BKP = BK + 8;   // LDS rows padded against bank conflicts
+
+__device__ __forceinline__ __bf16 to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);   // nearest even
+  const unsigned short h = (unsigned short)(u >> 16);
+  return __builtin_bit_cast(__bf16, h);
+}
+
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256)
+    k_gemm_bf16(const float *A, int lda, const float *B, int ldb, float *C, int ldc, int M, int N,
+                int K, const float *bias, int relu) {
+  __shared__ __bf16 As[BT][BKP];   // As[m][k]
+  __shared__ __bf16 Bs[BT][BKP];   // Bs[n][k]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+  const int m0 = blockIdx.x * BT, n0 = blockIdx.y * BT;
+  f32x4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    for (int e = tid; e < BT * BK; e += 256) {
+      int mm, kk;
+      if (TA) { kk = e % BK; mm = e / BK; } else { mm = e % BT; kk = e / BT; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      float av = 0.f;
+      if (gm < M && gk < K) av = TA ? A[gk + (int64_t)lda * gm] : A[gm + (int64_t)lda * gk];
+      As[mm][kk] = to_bf16(av);
+      int nn, kb;
+      if (TB) { nn = e % BT; kb = e / BT; } else { kb = e % BK; nn = e / BK; }
+      const int gn = n0 + nn, gk2 = k0 + kb;
+      float bv = 0.f;
+      if (gk2 < K && gn < N) bv = TB ? B[gn + (int64_t)ldb * gk2] : B[gk2 + (int64_t)ldb * gn];
+      Bs[nn][kb] = to_bf16(bv);
+    }
+    __syncthreads();
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+    bf16x8_t a[2], b[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        a[t][v] = As[32 * wr + 16 * t + r16][kq + v];
+        b[t][v] = Bs[32 * wc + 16 * t + r16][kq + v];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+  const int col = lane & 15, rb = (lane >> 4) * 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gm = m0 + 32 * wr + 16 * i + rb + v;
+        const int gn = n0 + 32 * wc + 16 * j + col;
+        if (gm < M && gn < N) {
+          float r = acc[i][j][v] + (bias ? bias[gm] : 0.f);
+          if (relu) r = r > 0.f ? r : 0.f;
+          C[gm + (int64_t)ldc * gn] = r;
+        }
+      }
+}
+
 // db[i] = sum_j dZ[i + M j]
 __global__ void k_rowsum(const float *dZ, int M, int N, float *db) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -146,7 +233,7 @@ __device__ void env_right(const float *X, const float *Y, const double *R, doubl
 // one block per sample j: loss_j and dOut column j (scaled by `scale`)
 __global__ void __launch_bounds__(256)
     k_tt_loss_grad(const float *out, const float *tgt, float *dout, double *loss, TTShape sh,
-                   double *scratch, int64_t per_sample, float scale) {
+                   double *scratch, int64_t per_sample, float scale, int angle) {
   const int j = blockIdx.x;
   const int64_t P = sh.off[sh.D];
   const float *x = out + P * j;
@@ -178,8 +265,14 @@ __global__ void __launch_bounds__(256)
   }
   const double xx = Lxx[D * env], xu = Lxu[D * env], uu = Luu[D * env];
   const double inv = uu > 0.0 ? 1.0 / uu : 0.0;
-  if (threadIdx.x == 0) loss[j] = (xx - 2.0 * xu + uu) * inv;
-  // gradient core k: 2 (Lxx X Rxx - Lxu U Rxu) / uu
+  // distance: L = (xx - 2 xu + uu) / uu, dL/dX = 2 (Gxx - Gxu) / uu;
+  // angle: L = 1 - xu^2 / (xx uu), dL/dX = 2 xu / (xx uu) (xu / xx Gxx - Gxu),
+  // with Gxx = Lxx X Rxx (half the gradient of xx) and Gxu = Lxu U Rxu
+  const bool ang = angle && xx > 0.0 && uu > 0.0;
+  const double cxx = ang ? 2.0 * xu * xu / (xx * xx * uu) : 2.0 * inv;
+  const double cxu = ang ? -2.0 * xu / (xx * uu) : -2.0 * inv;
+  if (threadIdx.x == 0) loss[j] = angle ? (ang ? 1.0 - xu * xu / (xx * uu) : 1.0)
+                                        : (xx - 2.0 * xu + uu) * inv;
   for (int k = 0; k < D; ++k) {
     const int r0 = sh.r[k], n = sh.n[k], r1 = sh.r[k + 1];
     const float *Xk = x + sh.off[k], *Uk = u + sh.off[k];
@@ -188,16 +281,17 @@ __global__ void __launch_bounds__(256)
     for (int e = threadIdx.x; e < r0 * n * r1; e += blockDim.x) {
       const int a = e % r0, ib = e / r0;
       const int i = ib % n, b = ib / n;
-      double s = 0.0;
+      double sx = 0.0, su = 0.0;
       for (int a2 = 0; a2 < r0; ++a2) {
         double tx = 0.0, tu = 0.0;
         for (int b2 = 0; b2 < r1; ++b2) {
           tx += (double)Xk[a2 + r0 * (i + n * b2)] * rxx[b + r1 * b2];
           tu += (double)Uk[a2 + r0 * (i + n * b2)] * rxu[b + r1 * b2];
         }
-        s += lxx[a + r0 * a2] * tx - lxu[a + r0 * a2] * tu;
+        sx += lxx[a + r0 * a2] * tx;
+        su += lxu[a + r0 * a2] * tu;
       }
-      g[sh.off[k] + e] = (float)(2.0 * s * inv) * scale;
+      g[sh.off[k] + e] = (float)(cxx * sx + cxu * su) * scale;
     }
   }
 }
@@ -302,7 +396,7 @@ __device__ void op_right(const float *X, const double *Ak, const float *Y, const
 __global__ void __launch_bounds__(256)
     k_tt_energy_loss_grad(const float *out, const float *tgt, float *dout, double *loss,
                           TTShape sh, OpShape op, double *scratch, int64_t per_sample,
-                          int64_t env_cap, int64_t w_cap, float scale) {
+                          int64_t env_cap, int64_t w_cap, float scale, int angle) {
   const int j = blockIdx.x;
   const int64_t P = sh.off[sh.D];
   const float *x = out + P * j;
@@ -315,6 +409,7 @@ __global__ void __launch_bounds__(256)
   double *Fxx = Pxu + (D + 1) * env_cap;       // current left environments
   double *Fxu = Fxx + env_cap, *Fuu = Fxu + env_cap, *Fn = Fuu + env_cap;
   double *W1 = Fn + env_cap, *W2 = W1 + w_cap, *W3 = W2 + w_cap;
+  double *Gx = W3 + w_cap, *Gu = Gx + P;       // angle: the two gradient parts
   if (threadIdx.x == 0) {
     Pxx[D * env_cap] = Pxu[D * env_cap] = 1.0;
     Fxx[0] = Fxu[0] = Fuu[0] = 1.0;
@@ -347,10 +442,16 @@ __global__ void __launch_bounds__(256)
         gx += W2[ai + (int64_t)r0 * n * bb] * pxx[b + (int64_t)r1 * bb];
         gu += W3[ai + (int64_t)r0 * n * bb] * pxu[b + (int64_t)r1 * bb];
       }
-      W1[e] = 2.0 * gx - 2.0 * gu;   // W1 is free again: keep the raw gradient
+      if (angle) {
+        Gx[sh.off[k] + e] = gx;
+        Gu[sh.off[k] + e] = gu;
+      } else {
+        W1[e] = 2.0 * gx - 2.0 * gu;   // W1 is free again: keep the raw gradient
+      }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < r0 * n * r1; e += blockDim.x) g[sh.off[k] + e] = (float)W1[e];
+    if (!angle)
+      for (int e = threadIdx.x; e < r0 * n * r1; e += blockDim.x) g[sh.off[k] + e] = (float)W1[e];
     __syncthreads();
     op_left_close(Xk, W2, Fn, r0, n, ra1, r1);
     for (int e = threadIdx.x; e < r1 * ra1 * r1; e += blockDim.x) Fxx[e] = Fn[e];
@@ -365,9 +466,52 @@ __global__ void __launch_bounds__(256)
   }
   const double xx = Fxx[0], xu = Fxu[0], uu = Fuu[0];
   const double inv = uu > 0.0 ? 1.0 / uu : 0.0;
+  if (angle) {
+    // L = 1 - xu^2 / (xx uu), dL/dX = 2 xu / (xx uu) (xu / xx Gx - Gu)
+    const bool ok = xx > 0.0 && uu > 0.0;
+    const double cxx = ok ? 2.0 * xu * xu / (xx * xx * uu) : 0.0;
+    const double cxu = ok ? -2.0 * xu / (xx * uu) : 0.0;
+    if (threadIdx.x == 0) loss[j] = ok ? 1.0 - xu * xu / (xx * uu) : 1.0;
+    for (int64_t e = threadIdx.x; e < P; e += blockDim.x)
+      g[e] = (float)(cxx * Gx[e] + cxu * Gu[e]) * scale;
+    return;
+  }
   if (threadIdx.x == 0) loss[j] = (xx - 2.0 * xu + uu) * inv;
   // scale the raw gradients by 1/<u, A u> and the batch factor
   for (int64_t e = threadIdx.x; e < P; e += blockDim.x) g[e] = (float)((double)g[e] * inv) * scale;
+}
+
+// one block per sample j: loss_j = ||x - u||^2 / ||u||^2 over the packed
+// cores themselves (targets in one fixed gauge) and dOut = 2 (x - u) / ||u||^2
+// times `scale`
+__global__ void __launch_bounds__(256)
+    k_core_loss_grad(const float *out, const float *tgt, float *dout, double *loss, int64_t P,
+                     float scale) {
+  __shared__ double red[2][256];
+  const int j = blockIdx.x;
+  const float *x = out + P * j;
+  const float *u = tgt + P * j;
+  float *g = dout + P * j;
+  double dd = 0.0, uu = 0.0;
+  for (int64_t e = threadIdx.x; e < P; e += blockDim.x) {
+    const double d = (double)x[e] - (double)u[e];
+    dd += d * d;
+    uu += (double)u[e] * (double)u[e];
+  }
+  red[0][threadIdx.x] = dd;
+  red[1][threadIdx.x] = uu;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + o];
+      red[1][threadIdx.x] += red[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  const double inv = red[1][0] > 0.0 ? 1.0 / red[1][0] : 0.0;
+  if (threadIdx.x == 0) loss[j] = red[0][0] * inv;
+  for (int64_t e = threadIdx.x; e < P; e += blockDim.x)
+    g[e] = (float)(2.0 * ((double)x[e] - (double)u[e]) * inv) * scale;
 }
 
 __global__ void k_mean(const double *v, int n, double *out) {
@@ -399,8 +543,21 @@ int64_t param_count(int nl, const int32_t *sz) {
 }
 
 hipError_t gemm(bool ta, bool tb, const float *A, int lda, const float *B, int ldb, float *C,
-                int ldc, int M, int N, int K, const float *bias, int relu, hipStream_t s) {
+                int ldc, int M, int N, int K, const float *bias, int relu, hipStream_t s,
+                bool bf16 = false) {
   dim3 grid((M + TM - 1) / TM, (N + TM - 1) / TM);
+  if (bf16) {
+    if (!ta && !tb)
+      hipLaunchKernelGGL((k_gemm_bf16<false, false>), grid, dim3(256), 0, s, A, lda, B, ldb, C,
+                         ldc, M, N, K, bias, relu);
+    else if (ta && !tb)
+      hipLaunchKernelGGL((k_gemm_bf16<true, false>), grid, dim3(256), 0, s, A, lda, B, ldb, C,
+                         ldc, M, N, K, bias, relu);
+    else
+      hipLaunchKernelGGL((k_gemm_bf16<false, true>), grid, dim3(256), 0, s, A, lda, B, ldb, C,
+                         ldc, M, N, K, bias, relu);
+    return hipGetLastError();
+  }
   if (!ta && !tb)
     hipLaunchKernelGGL((k_gemm32<false, false>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc,
                        M, N, K, bias, relu);
@@ -416,6 +573,10 @@ hipError_t gemm(bool ta, bool tb, const float *A, int lda, const float *B, int l
 qtt_status check_net(const qtt_mlp *net) {
   if (!net || !net->sizes || !net->params) return fail(QTT_E_INVAL, "net: NULL field");
   if (net->nlayers < 1 || net->nlayers > 16) return fail(QTT_E_INVAL, "nlayers must be 1..16");
+  if (net->gemm_dtype != QTT_F64 && net->gemm_dtype != QTT_F32 && net->gemm_dtype != QTT_BF16)
+    return fail(QTT_E_INVAL, "gemm_dtype must be QTT_F32 or QTT_BF16");
+  if (net->loss != QTT_LOSS_TT && net->loss != QTT_LOSS_CORES && net->loss != QTT_LOSS_ANGLE)
+    return fail(QTT_E_INVAL, "loss must be QTT_LOSS_TT, QTT_LOSS_CORES or QTT_LOSS_ANGLE");
   for (int l = 0; l <= net->nlayers; ++l)
     if (net->sizes[l] < 1 || net->sizes[l] > (1 << 20)) return fail(QTT_E_INVAL, "bad layer size");
   return QTT_OK;
@@ -462,8 +623,8 @@ bool carve_mlp(Arena &ar, const qtt_mlp *net, int B, const TTShape *sh, MlpWs &w
     w.per_sample = 5 * (sh->D + 1) * env + tm;
     if (metric_ranks) {
       energy_caps(*sh, metric_ranks, w.env_cap, w.w_cap);
-      w.per_sample = std::max<int64_t>(w.per_sample,
-                                       (2 * (sh->D + 1) + 4) * w.env_cap + 3 * w.w_cap);
+      w.per_sample = std::max<int64_t>(
+          w.per_sample, (2 * (sh->D + 1) + 4) * w.env_cap + 3 * w.w_cap + 2 * sh->off[sh->D]);
     }
     w.scratch = (double *)ar.take(sizeof(double) * w.per_sample * B);
   }
@@ -521,7 +682,7 @@ hipError_t forward(const qtt_mlp *net, const float *a, int B, MlpWs &w, hipStrea
     const int in = net->sizes[l], out = net->sizes[l + 1];
     const float *W = p, *b = p + (int64_t)out * in;
     hipError_t e = gemm(false, false, W, out, h, in, w.H[l + 1], out, out, B, in, b,
-                        l < nl - 1 ? 1 : 0, s);
+                        l < nl - 1 ? 1 : 0, s, net->gemm_dtype == QTT_BF16);
     if (e != hipSuccess) return e;
     h = w.H[l + 1];
     p += (int64_t)out * in + out;
@@ -553,6 +714,8 @@ extern "C" qtt_status qtt_warmstart_workspace(const qtt_mlp *net, int32_t batch,
   }
   OpShape op;
   if (psh && (st = check_metric(metric, sh, op)) != QTT_OK) return st;
+  if (metric && net->loss == QTT_LOSS_CORES)
+    return fail(QTT_E_INVAL, "QTT_LOSS_CORES takes no metric");
   Arena ar;
   ar.dry = true;
   MlpWs w;
@@ -581,6 +744,96 @@ extern "C" qtt_status qtt_warmstart_infer(const qtt_mlp *net, const float *a, in
   return QTT_OK;
 }
 
+namespace qtt {
+namespace {
+
+// one Adam step on a batch already in device memory; the batch's mean loss
+// is left in w.lmean[0] (device), nothing is synchronised
+qtt_status train_batch(qtt_mlp *net, const float *a, const float *targets, int batch,
+                       const TTShape &sh, const OpShape *op, float lr, MlpWs &w, hipStream_t s) {
+  const int nl = net->nlayers;
+  QTT_HIP(forward(net, a, batch, w, s));
+  // dL/dOut (mean over the batch) and the per-sample losses
+  if (net->loss == QTT_LOSS_CORES)
+    hipLaunchKernelGGL(k_core_loss_grad, dim3(batch), dim3(256), 0, s, w.H[nl], targets, w.dA,
+                       w.loss, sh.off[sh.D], 1.0f / batch);
+  else if (op)
+    hipLaunchKernelGGL(k_tt_energy_loss_grad, dim3(batch), dim3(256), 0, s, w.H[nl], targets, w.dA,
+                       w.loss, sh, *op, w.scratch, w.per_sample, w.env_cap, w.w_cap,
+                       1.0f / batch, net->loss == QTT_LOSS_ANGLE ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_tt_loss_grad, dim3(batch), dim3(256), 0, s, w.H[nl], targets, w.dA,
+                       w.loss, sh, w.scratch, w.per_sample, 1.0f / batch,
+                       net->loss == QTT_LOSS_ANGLE ? 1 : 0);
+  QTT_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_mean, dim3(1), dim3(64), 0, s, w.loss, batch, w.lmean);
+  // backward, last layer first; offsets of each layer's parameters
+  std::vector<int64_t> off(nl + 1, 0);
+  for (int l = 0; l < nl; ++l)
+    off[l + 1] = off[l] + (int64_t)net->sizes[l + 1] * net->sizes[l] + net->sizes[l + 1];
+  float *dcur = w.dA, *dnext = w.dB;
+  const bool bf = net->gemm_dtype == QTT_BF16;
+  for (int l = nl - 1; l >= 0; --l) {
+    const int in = net->sizes[l], out = net->sizes[l + 1];
+    const float *W = net->params + off[l];
+    float *gW = w.grad + off[l], *gb = gW + (int64_t)out * in;
+    const float *hprev = l == 0 ? a : w.H[l];
+    // dW = dZ H_prev^T, db = rowsum(dZ)
+    QTT_HIP(gemm(false, true, dcur, out, hprev, in, gW, out, out, in, batch, nullptr, 0, s, bf));
+    hipLaunchKernelGGL(k_rowsum, dim3((out + 255) / 256), dim3(256), 0, s, dcur, out, batch, gb);
+    QTT_HIP(hipGetLastError());
+    if (l > 0) {
+      // dH_prev = W^T dZ, then the ReLU mask of layer l
+      QTT_HIP(gemm(true, false, W, out, dcur, out, dnext, in, in, batch, out, nullptr, 0, s, bf));
+      const int64_t ne = (int64_t)in * batch;
+      hipLaunchKernelGGL(k_relu_mask, dim3((int)std::min<int64_t>((ne + 255) / 256, 4096)),
+                         dim3(256), 0, s, dnext, w.H[l], ne);
+      QTT_HIP(hipGetLastError());
+      std::swap(dcur, dnext);
+    }
+  }
+  const int64_t np = off[nl];
+  const double t = (double)(net->step + 1);
+  const float c1 = (float)(1.0 - std::pow(0.9, t)), c2 = (float)(1.0 - std::pow(0.999, t));
+  hipLaunchKernelGGL(k_adam, dim3((int)std::min<int64_t>((np + 255) / 256, 8192)), dim3(256), 0,
+                     s, net->params, w.grad, net->adam_m, net->adam_v, np, lr, c1, c2);
+  QTT_HIP(hipGetLastError());
+  net->step += 1;
+  return QTT_OK;
+}
+
+// dst[:, j] = src[:, idx[j]] for FP32 columns of length len
+__global__ void k_gather_cols(const float *src, const int *idx, int len, int ncols, float *dst) {
+  const int64_t ne = (int64_t)len * ncols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e / len), r = (int)(e % len);
+    dst[e] = src[r + (int64_t)len * idx[j]];
+  }
+}
+
+// acc[0] += c * v[0]
+__global__ void k_accum(double *acc, const double *v, double c) { acc[0] += c * v[0]; }
+__global__ void k_zero1(double *p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
+}
+// FP32 column -> FP64 train
+__global__ void k_f32_to_f64(const float *src, double *dst, int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = (double)src[e];
+}
+
+uint64_t splitmix64(uint64_t &x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace
+}  // namespace qtt
+
 extern "C" qtt_status qtt_warmstart_train_step(qtt_mlp *net, const float *a, const float *targets,
                                                int32_t batch, int32_t ncores, const int32_t *nrow,
                                                const int32_t *ranks, const qtt_tt *metric,
@@ -597,6 +850,8 @@ extern "C" qtt_status qtt_warmstart_train_step(qtt_mlp *net, const float *a, con
   if ((st = make_shape(ncores, nrow, ranks, net->sizes[nl], sh)) != QTT_OK) return st;
   OpShape op;
   if ((st = check_metric(metric, sh, op)) != QTT_OK) return st;
+  if (metric && net->loss == QTT_LOSS_CORES)
+    return fail(QTT_E_INVAL, "QTT_LOSS_CORES takes no metric");
   Arena ar;
   ar.base = (char *)ws;
   ar.size = ws_bytes;
@@ -604,51 +859,125 @@ extern "C" qtt_status qtt_warmstart_train_step(qtt_mlp *net, const float *a, con
   if (!ws || !carve_mlp(ar, net, batch, &sh, w, metric ? metric->ranks : nullptr))
     return fail(QTT_E_CAPACITY, "workspace too small for qtt_warmstart_train_step");
   hipStream_t s = (hipStream_t)stream;
-  QTT_HIP(forward(net, a, batch, w, s));
-  // dL/dOut (mean over the batch) and the per-sample losses
-  if (metric)
-    hipLaunchKernelGGL(k_tt_energy_loss_grad, dim3(batch), dim3(256), 0, s, w.H[nl], targets, w.dA,
-                       w.loss, sh, op, w.scratch, w.per_sample, w.env_cap, w.w_cap,
-                       1.0f / batch);
-  else
-    hipLaunchKernelGGL(k_tt_loss_grad, dim3(batch), dim3(256), 0, s, w.H[nl], targets, w.dA,
-                       w.loss, sh, w.scratch, w.per_sample, 1.0f / batch);
-  QTT_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_mean, dim3(1), dim3(64), 0, s, w.loss, batch, w.lmean);
-  // backward, last layer first; offsets of each layer's parameters
-  std::vector<int64_t> off(nl + 1, 0);
-  for (int l = 0; l < nl; ++l)
-    off[l + 1] = off[l] + (int64_t)net->sizes[l + 1] * net->sizes[l] + net->sizes[l + 1];
-  float *dcur = w.dA, *dnext = w.dB;
-  for (int l = nl - 1; l >= 0; --l) {
-    const int in = net->sizes[l], out = net->sizes[l + 1];
-    const float *W = net->params + off[l];
-    float *gW = w.grad + off[l], *gb = gW + (int64_t)out * in;
-    const float *hprev = l == 0 ? a : w.H[l];
-    // dW = dZ H_prev^T, db = rowsum(dZ)
-    QTT_HIP(gemm(false, true, dcur, out, hprev, in, gW, out, out, in, batch, nullptr, 0, s));
-    hipLaunchKernelGGL(k_rowsum, dim3((out + 255) / 256), dim3(256), 0, s, dcur, out, batch, gb);
-    QTT_HIP(hipGetLastError());
-    if (l > 0) {
-      // dH_prev = W^T dZ, then the ReLU mask of layer l
-      QTT_HIP(gemm(true, false, W, out, dcur, out, dnext, in, in, batch, out, nullptr, 0, s));
-      const int64_t ne = (int64_t)in * batch;
-      hipLaunchKernelGGL(k_relu_mask, dim3((int)std::min<int64_t>((ne + 255) / 256, 4096)),
-                         dim3(256), 0, s, dnext, w.H[l], ne);
-      QTT_HIP(hipGetLastError());
-      std::swap(dcur, dnext);
-    }
-  }
-  const int64_t np = off[nl];
-  const double t = (double)(net->step + 1);
-  const float c1 = (float)(1.0 - std::pow(0.9, t)), c2 = (float)(1.0 - std::pow(0.999, t));
-  hipLaunchKernelGGL(k_adam, dim3((int)std::min<int64_t>((np + 255) / 256, 8192)), dim3(256), 0,
-                     s, net->params, w.grad, net->adam_m, net->adam_v, np, lr, c1, c2);
-  QTT_HIP(hipGetLastError());
-  net->step += 1;
+  if ((st = train_batch(net, a, targets, batch, sh, metric ? &op : nullptr, lr, w, s)) != QTT_OK)
+    return st;
   double lm = 0.0;
   QTT_HIP(hipMemcpyAsync(&lm, w.lmean, sizeof(double), hipMemcpyDeviceToHost, s));
   QTT_HIP(hipStreamSynchronize(s));
   if (loss) *loss = lm;
+  return QTT_OK;
+}
+
+extern "C" qtt_status qtt_warmstart_fit_workspace(const qtt_mlp *net, int32_t n, int32_t batch,
+                                                  int32_t ncores, const int32_t *nrow,
+                                                  const int32_t *ranks, const qtt_tt *metric,
+                                                  size_t *bytes) {
+  qtt_status st = qtt_warmstart_workspace(net, batch, ncores, nrow, ranks, metric, bytes);
+  if (st != QTT_OK) return st;
+  if (n < 1) return fail(QTT_E_INVAL, "n >= 1 required");
+  const int nin = net->sizes[0], nout = net->sizes[net->nlayers];
+  // batch copies of inputs and targets, the sample order, the epoch losses
+  *bytes += 256 * 6 + sizeof(float) * ((int64_t)nin + nout) * batch + sizeof(int) * (int64_t)n +
+            sizeof(double) * 4096;
+  return QTT_OK;
+}
+
+extern "C" qtt_status qtt_warmstart_fit(qtt_mlp *net, const float *a, const float *targets,
+                                        int32_t n, int32_t batch, int32_t epochs, float lr,
+                                        float lr_final, uint64_t seed, int32_t ncores,
+                                        const int32_t *nrow, const int32_t *ranks,
+                                        const qtt_tt *metric, double *loss_hist, void *ws,
+                                        size_t ws_bytes, void *stream) {
+  qtt::clear_stale_error();
+  qtt_status st = check_net(net);
+  if (st != QTT_OK) return st;
+  if (!a || !targets || n < 1 || batch < 1 || batch > n || epochs < 1 || epochs > 4096)
+    return fail(QTT_E_INVAL, "a, targets, 1 <= batch <= n and 1 <= epochs <= 4096 required");
+  if (!net->adam_m || !net->adam_v) return fail(QTT_E_INVAL, "Adam moments are NULL");
+  if (!(lr > 0.f) || !(lr_final > 0.f)) return fail(QTT_E_INVAL, "lr and lr_final must be > 0");
+  const int nl = net->nlayers;
+  const int nin = net->sizes[0], nout = net->sizes[nl];
+  TTShape sh;
+  if ((st = make_shape(ncores, nrow, ranks, nout, sh)) != QTT_OK) return st;
+  OpShape op;
+  if ((st = check_metric(metric, sh, op)) != QTT_OK) return st;
+  if (metric && net->loss == QTT_LOSS_CORES)
+    return fail(QTT_E_INVAL, "QTT_LOSS_CORES takes no metric");
+  Arena ar;
+  ar.base = (char *)ws;
+  ar.size = ws_bytes;
+  MlpWs w;
+  bool ok = ws && carve_mlp(ar, net, batch, &sh, w, metric ? metric->ranks : nullptr);
+  float *ab = (float *)ar.take(sizeof(float) * (int64_t)nin * batch);
+  float *tb = (float *)ar.take(sizeof(float) * (int64_t)nout * batch);
+  int *order = (int *)ar.take(sizeof(int) * (int64_t)n);
+  double *hist = (double *)ar.take(sizeof(double) * 4096);
+  if (!ok || !ar.ok()) return fail(QTT_E_CAPACITY, "workspace too small for qtt_warmstart_fit");
+  hipStream_t s = (hipStream_t)stream;
+  const int nb = n / batch;          // full batches per epoch (the rest is reshuffled)
+  const int64_t steps = (int64_t)nb * epochs;
+  std::vector<int> perm(n);
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  uint64_t rs = seed;
+  hipLaunchKernelGGL(k_zero1, dim3(1), dim3(256), 0, s, hist, epochs);
+  int64_t step = 0;
+  for (int ep = 0; ep < epochs; ++ep) {
+    // Fisher-Yates shuffle with splitmix64 (Steele, Lea and Flood 2014)
+    for (int i = n - 1; i > 0; --i) {
+      const int j = (int)(splitmix64(rs) % (uint64_t)(i + 1));
+      std::swap(perm[i], perm[j]);
+    }
+    QTT_HIP(hipMemcpyAsync(order, perm.data(), sizeof(int) * (int64_t)n, hipMemcpyHostToDevice, s));
+    for (int b = 0; b < nb; ++b, ++step) {
+      const int gb = (int)std::min<int64_t>(((int64_t)nin * batch + 255) / 256, 2048);
+      hipLaunchKernelGGL(k_gather_cols, dim3(gb), dim3(256), 0, s, a, order + (int64_t)b * batch,
+                         nin, batch, ab);
+      const int gt = (int)std::min<int64_t>(((int64_t)nout * batch + 255) / 256, 4096);
+      hipLaunchKernelGGL(k_gather_cols, dim3(gt), dim3(256), 0, s, targets,
+                         order + (int64_t)b * batch, nout, batch, tb);
+      QTT_HIP(hipGetLastError());
+      // cosine decay of the learning rate from lr to lr_final
+      const double fr = steps > 1 ? (double)step / (double)(steps - 1) : 1.0;
+      const float lrs = (float)(lr_final + 0.5 * (lr - lr_final) * (1.0 + std::cos(M_PI * fr)));
+      if ((st = train_batch(net, ab, tb, batch, sh, metric ? &op : nullptr, lrs, w, s)) != QTT_OK)
+        return st;
+      hipLaunchKernelGGL(k_accum, dim3(1), dim3(1), 0, s, hist + ep, w.lmean, 1.0 / nb);
+    }
+    // the host order array is reused next epoch: wait for its copy
+    QTT_HIP(hipStreamSynchronize(s));
+  }
+  if (loss_hist)
+    QTT_HIP(hipMemcpyAsync(loss_hist, hist, sizeof(double) * epochs, hipMemcpyDeviceToHost, s));
+  QTT_HIP(hipStreamSynchronize(s));
+  return QTT_OK;
+}
+
+extern "C" qtt_status qtt_warmstart_infer_tt(const qtt_mlp *net, const float *a, int32_t ncores,
+                                             const int32_t *nrow, const int32_t *ranks,
+                                             qtt_tt *x0, void *ws, size_t ws_bytes, void *stream) {
+  qtt::clear_stale_error();
+  qtt_status st = check_net(net);
+  if (st != QTT_OK) return st;
+  if (!a || !x0 || !x0->data || !x0->ranks || !x0->nrow || x0->ncol)
+    return fail(QTT_E_INVAL, "a and a vector x0 required");
+  const int nout = net->sizes[net->nlayers];
+  TTShape sh;
+  if ((st = make_shape(ncores, nrow, ranks, nout, sh)) != QTT_OK) return st;
+  if (x0->ncores != ncores) return fail(QTT_E_SHAPE, "x0 core count differs");
+  for (int k = 0; k < ncores; ++k)
+    if (x0->nrow[k] != nrow[k]) return fail(QTT_E_SHAPE, "x0 modes differ");
+  if (x0->capacity < nout) return fail(QTT_E_CAPACITY, "x0: capacity below the packed size");
+  Arena ar;
+  ar.base = (char *)ws;
+  ar.size = ws_bytes;
+  MlpWs w;
+  if (!ws || !carve_mlp(ar, net, 1, nullptr, w))
+    return fail(QTT_E_CAPACITY, "workspace too small for qtt_warmstart_infer_tt");
+  hipStream_t s = (hipStream_t)stream;
+  QTT_HIP(forward(net, a, 1, w, s));
+  hipLaunchKernelGGL(k_f32_to_f64, dim3((int)std::min<int64_t>((nout + 255) / 256, 1024)),
+                     dim3(256), 0, s, w.H[net->nlayers], x0->data, (int64_t)nout);
+  QTT_HIP(hipGetLastError());
+  for (int k = 0; k <= ncores; ++k) x0->ranks[k] = ranks[k];
   return QTT_OK;
 }

@@ -15,6 +15,7 @@
 // is a fixed sequence of launches with no host round trip.  The QR and SVD
 // steps of one core run in one workgroup; the GEMMs of absorb and fold use
 // the whole chip.
+#include "dev_gemm.h"
 #include "internal.h"
 
 namespace qtt {
@@ -219,49 +220,9 @@ __global__ void __launch_bounds__(WG)
   if (threadIdx.x == 0) w.nr[k + 1] = rq;
 }
 
-// Column-major GEMM C = A * B, 64x64 tiles, K step 16, FP64.
-constexpr int GT = 64, GK = 16;
-__device__ void gemm_tile(const double *A, int lda, const double *B, int ldb,
-                          double *C, int ldc, int M, int N, int K, int tm,
-                          int tn) {
-  __shared__ double As[GK][GT + 1];
-  __shared__ double Bs[GK][GT + 1];
-  const int tid = threadIdx.x;  // 256 threads
-  const int tr = tid % 16, tc = tid / 16;
-  double acc[4][4] = {};
-  const int m0 = tm * GT, n0 = tn * GT;
-  for (int k0 = 0; k0 < K; k0 += GK) {
-    for (int e = tid; e < GK * GT; e += 256) {
-      const int mm = e % GT, kk = e / GT;
-      const int gm = m0 + mm, gk = k0 + kk;
-      As[kk][mm] = (gm < M && gk < K) ? A[gm + (int64_t)lda * gk] : 0.0;
-      const int kk2 = e % GK, nn = e / GK;
-      const int gk2 = k0 + kk2, gn = n0 + nn;
-      Bs[kk2][nn] = (gk2 < K && gn < N) ? B[gk2 + (int64_t)ldb * gn] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < GK; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = As[kk][tr + 16 * u];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) b[v] = Bs[kk][tc + 16 * v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int gm = m0 + tr + 16 * u, gn = n0 + tc + 16 * v;
-      if (gm < M && gn < N) C[gm + (int64_t)ldc * gn] = acc[u][v];
-    }
-}
+// Column-major FP64 GEMM tiles of dev_gemm.h (64 x 64 per 256-thread block)
+using dev::GT;
+using dev::gemm_tile;
 
 // absorb: carry (nr[k+1] x nm_{k+1} rk[k+2]) = R (nr[k+1] x rk[k+1]) *
 // slot k+1 (rk[k+1] x nm_{k+1} rk[k+2])
@@ -273,8 +234,8 @@ __global__ void __launch_bounds__(256)
   const int N = x.n[k + 1] * x.m[k + 1] * x.rk[k + 2];
   if (M > x.cap[k + 1] || K > x.cap[k + 1] || x.rk[k + 2] > x.cap[k + 2]) return;
   if (blockIdx.x * GT >= M || blockIdx.y * GT >= N) return;
-  gemm_tile(rbuf, M, x.data + x.off[k + 1], K, carry, M, M, N, K, blockIdx.x,
-            blockIdx.y);
+  gemm_tile<false>(rbuf, M, x.data + x.off[k + 1], K, carry, M, M, N, K, blockIdx.x,
+                   blockIdx.y);
 }
 
 // fold: carry ((nr[k-1] nm_{k-1}) x fr[k]) = slot k-1 ((nr[k-1] nm) x nr[k])
@@ -287,8 +248,8 @@ __global__ void __launch_bounds__(256)
   const int N = w.fr[k];
   if (w.nr[k - 1] > x.cap[k - 1] || K > x.cap[k] || N > x.cap[k]) return;
   if (blockIdx.x * GT >= M || blockIdx.y * GT >= N) return;
-  gemm_tile(x.data + x.off[k - 1], M, F, K, carry, M, M, N, K, blockIdx.x,
-            blockIdx.y);
+  gemm_tile<false>(x.data + x.off[k - 1], M, F, K, carry, M, M, N, K, blockIdx.x,
+                   blockIdx.y);
 }
 
 // norm of the last core after the QR sweep
@@ -678,12 +639,13 @@ bool round_ws_take(Arena &ar, const TTView &x, RoundWs &w) {
   const int64_t slot = max_slot(x);
   const int64_t cap = max_cap(x);
   const int64_t nm = max_nm(x);
-  // SVD matrices are at most cap x (nm cap); V at most (nm cap)^2
-  const int64_t sq = (nm * cap) * (nm * cap);
+  // work holds the QR step's (r n m) x r' block and the SVD step's unfolding
+  // (or its transpose) or the wide case's r' x rank product, each at most
+  // the largest slot; the Jacobi V (at most cap x cap) lives in vbuf
   w.carry_elems = slot;
-  w.sq_elems = sq;
+  w.sq_elems = slot;
   w.carry = (double *)ar.take(sizeof(double) * slot);
-  w.work = (double *)ar.take(sizeof(double) * (slot > sq ? slot : sq));
+  w.work = (double *)ar.take(sizeof(double) * slot);
   w.rbuf = (double *)ar.take(sizeof(double) * cap * cap);
   w.vbuf = (double *)ar.take(sizeof(double) * cap * cap);
   w.fold = (double *)ar.take(sizeof(double) * cap * cap * nm);

@@ -20,7 +20,7 @@ namespace {
 
 constexpr int MV_TX = 64;   // lanes along b (output rows of one column)
 constexpr int MV_TY = 4;    // waves along a
-constexpr int MV_MMAX = 8;  // largest column mode handled
+constexpr int MV_MMAX = 8;  // column modes held in registers (wider ones read directly)
 
 template <typename T>
 __device__ __forceinline__ float to_compute(double v);
@@ -166,6 +166,18 @@ __global__ void __launch_bounds__(MV_TX *MV_TY)
     for (int b0 = 0; b0 < rx0; b0 += MV_TX) {
       const int b = b0 + tx;
       const bool act = b < rx0;
+      if (m > MV_MMAX) {
+        // wide column modes (a subdomain core): operands straight from memory
+        for (int a = ty; a < ra0; a += MV_TY) {
+          const double *Aa = Ak + a + (int64_t)ra0 * (i + (int64_t)n * m * c);
+          double acc = 0.0;
+          if (act)
+            for (int j = 0; j < m; ++j)
+              acc = fma(Aa[(int64_t)ra0 * n * j], xk[b + (int64_t)rx0 * (j + (int64_t)m * d)], acc);
+          if (act) __builtin_nontemporal_store(acc, &ycol[a * rx0 + b]);
+        }
+        continue;
+      }
       double xv[MV_MMAX];
 #pragma unroll
       for (int j = 0; j < MV_MMAX; ++j)
@@ -211,6 +223,18 @@ __global__ void __launch_bounds__(MV_TX *MV_TY)
     for (int b0 = 0; b0 < rx0; b0 += MV_TX) {
       const int b = b0 + tx;
       const bool act = b < rx0;
+      if (m > MV_MMAX) {
+        for (int a = ty; a < ra0; a += MV_TY) {
+          const double *Aa = Ak + a + (int64_t)ra0 * (i + (int64_t)n * m * c);
+          float acc = 0.0f;
+          if (act)
+            for (int j = 0; j < m; ++j)
+              acc = fmaf(to_compute<T>(Aa[(int64_t)ra0 * n * j]),
+                         to_compute<T>(xk[b + (int64_t)rx0 * (j + (int64_t)m * d)]), acc);
+          if (act) __builtin_nontemporal_store(static_cast<double>(acc), &ycol[a * rx0 + b]);
+        }
+        continue;
+      }
       float xv[MV_MMAX];
 #pragma unroll
       for (int j = 0; j < MV_MMAX; ++j)

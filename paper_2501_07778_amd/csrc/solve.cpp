@@ -189,7 +189,7 @@ void packed_view_of(const qtt_tt *t, TTView &v, int32_t *rk) {
 
 qtt_status check_opts(const qtt_solve_opts *o) {
   if (!o) return fail(QTT_E_INVAL, "opts is NULL");
-  if (o->method == QTT_SOLVE_ALS) return check_als_opts(o);
+  if (o->method == QTT_SOLVE_ALS || o->method == QTT_SOLVE_AMEN) return check_als_opts(o);
   if (!(o->tol > 0.0) || !(o->eps >= 0.0) || !(o->eps_in >= 0.0) || !(o->red_in > 0.0))
     return fail(QTT_E_INVAL, "tolerances must be positive");
   if (o->rmax < 1 || o->rmax_in < 1 || o->rmax > 4096 || o->rmax_in > 4096)
@@ -254,7 +254,7 @@ extern "C" qtt_status qtt_solve_workspace(const qtt_tt *K, const qtt_tt *f,
   if ((st = check_opts(o)) != QTT_OK) return st;
   if ((st = check_precond(K, o->precond)) != QTT_OK) return st;
   if (!bytes) return fail(QTT_E_INVAL, "bytes is NULL");
-  if (o->method == QTT_SOLVE_ALS) {
+  if (o->method == QTT_SOLVE_ALS || o->method == QTT_SOLVE_AMEN) {
     *bytes = als_workspace_bytes(K, f, o);
     return QTT_OK;
   }
@@ -290,7 +290,7 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
         return fail(QTT_E_SHAPE, "x0 rank exceeds rmax or the mode-product bound");
   }
   if (!ws) return fail(QTT_E_CAPACITY, "workspace is NULL");
-  if (o->method == QTT_SOLVE_ALS)
+  if (o->method == QTT_SOLVE_ALS || o->method == QTT_SOLVE_AMEN)
     return solve_als(K, f, x0, o, u, rep, ws, ws_bytes, (hipStream_t)stream);
   Arena ar;
   ar.base = (char *)ws;
@@ -672,6 +672,7 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
   }
   R.max_rank = mr;
   R.status = converged ? QTT_OK : QTT_E_NOCONV;
+  R.warm_start = x0 ? 1 : 0;
   if (rep) *rep = R;
   if (!converged) return fail(QTT_E_NOCONV, "tolerance not reached");
   return QTT_OK;

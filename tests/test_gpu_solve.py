@@ -343,3 +343,49 @@ def test_batched_solves_equal_single_solves(P):
     assert best in rates and all(r > 0 for r in rates.values())
     st = [r["status"] for _, r in small.results()]
     assert st == [0, -4, 0], st
+
+
+@pytest.mark.parametrize("d", [2, 3, 5])
+@pytest.mark.parametrize("which", ["skewed", "strip"])
+def test_assembly_of_parallelogram_and_strip_matches_sparse_fem(P, d, which):
+    """Non-square subdomains (a parallelogram, stiffness from the constant
+    Jacobian of its affine map) and the paper's cantilever strip of 20
+    square subdomains (uniform tip traction, plane stress, E = 64, nu = 0):
+    the QTT operator and load equal the element-loop sparse FEM in Z-order."""
+    if which == "strip" and d == 5:
+        d = 4
+    prob = W.skewed_cantilever(d) if which == "skewed" else W.cantilever_strip(d)
+    Kt, ft = P.assemble(prob)
+    K, f, _, _ = fem.assemble_system(prob)
+    Kz = fem.permute_matrix_to_qtt(K, d, prob.q).toarray()
+    fz = fem.to_qtt_order(f, d, prob.q)
+    np.testing.assert_allclose(T.full_matrix(P.tt_to_cores(Kt)), Kz, atol=1e-12 * np.abs(Kz).max())
+    np.testing.assert_allclose(T.full_vector(P.tt_to_cores(ft)), fz, atol=1e-12 * np.abs(fz).max())
+
+
+@pytest.mark.parametrize("which,d,rmax,bound", [("skewed", 5, 64, 1e-9), ("strip", 3, 128, 1e-7),
+                                                 ("strip", 5, 64, 2e-5)])
+def test_solve_parallelogram_and_strip_against_direct(P, which, d, rmax, bound):
+    """The parallelogram subdomain by ALS at full rank (the mode-product
+    bounds): the oracle's sparse direct solve to 1e-9.  The cantilever
+    strip (20 squares in a row, aspect ratio 20) by AMEn: its conditioning
+    puts a floor under the per-sweep change (near 5e-8 at level 3 and 2e-6
+    at level 5, 40,960 dofs, where one-site ALS at rank 48 stalls too), so
+    the stop tolerances are 1e-7 and 3e-6 and the errors against the direct
+    solve 1e-7 and 2e-5 (measured 2.0e-8 in 8 sweeps and 3.9e-6 in 12)."""
+    prob = W.skewed_cantilever(d) if which == "skewed" else W.cantilever_strip(d)
+    uref, _ = fem.solve_problem(prob)
+    K, f = P.assemble(prob)
+    if which == "skewed":
+        opts = P.SolveOpts(tol=1e-10, eps=0.0, rmax=rmax, maxit_out=30, rmax_in=0, method="als",
+                           seed=1)
+    else:
+        opts = P.SolveOpts(tol=1e-7 if d == 3 else 3e-6, eps=1e-10, rmax=rmax, rmax_in=8,
+                           eps_in=1e-2, maxit_out=80, method="amen", seed=1)
+    print("solve %s d=%d rank %d" % (which, d, rmax), flush=True)
+    u, rep = P.solve(K, f, opts)
+    assert rep["status"] == 0, rep
+    err = np.linalg.norm(T.full_vector(P.tt_to_cores(u)) - uref) / np.linalg.norm(uref)
+    print("%s d=%d: error %.2e, sweeps %d, rank %d" % (which, d, err, rep["outer"],
+                                                      rep["max_rank"]), flush=True)
+    assert err <= bound, err

@@ -211,3 +211,81 @@ def test_mesh_convergence_tip_displacement():
         vals.append(u[2 * tip + 1].mean())
     diffs = np.abs(np.diff(vals))
     assert diffs[1] < diffs[0] / 2.5 and diffs[2] < diffs[1] / 2.5
+
+
+@pytest.mark.parametrize("d", [2, 3, 4])
+def test_parallelogram_subdomain_null_modes_patch_and_area(d):
+    """A parallelogram subdomain (edge vectors (1.3, 0) and (0.4, 1)): rigid
+    modes in the null space, the patch test (a linear field leaves zero
+    residual at interior nodes), total mass = area |det A|."""
+    sq = W.skewed_cantilever(d).subs[0]
+    C = fem.c_matrix(1.0, 0.3)
+    K, M = fem.assemble_square(d, sq.x0, sq.y0, sq.side, C, sq.edges)
+    n = 2 ** d
+    x, y = fem.node_coords(d, sq)
+    assert abs(K - K.T).max() < 1e-15 * abs(K).max()
+    u = np.zeros(2 * n * n)
+    for mode in range(3):
+        u[:] = 0
+        if mode == 0:
+            u[0::2] = 1
+        elif mode == 1:
+            u[1::2] = 1
+        else:
+            u[0::2] = -y
+            u[1::2] = x
+        assert np.abs(K @ u).max() < 1e-13 * abs(K).max()
+    u[0::2] = 0.3 + 0.7 * x - 0.2 * y
+    u[1::2] = -0.1 + 0.4 * x + 0.9 * y
+    r = K @ u
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    interior = ((i > 0) & (i < n - 1) & (j > 0) & (j < n - 1)).ravel(order="F")
+    assert np.abs(r[0::2][interior]).max() < 1e-12 * abs(K).max()
+    assert np.abs(r[1::2][interior]).max() < 1e-12 * abs(K).max()
+    assert M.sum() == pytest.approx(1.3 * 1.0 - 0.0 * 0.4, rel=1e-13)
+
+
+def test_rotated_square_equals_rotated_stiffness():
+    """A unit square rotated by 30 degrees (edges (c, s), (-s, c)) has the
+    stiffness of the axis-aligned square with every nodal displacement
+    rotated: K_rot = Q K Q^T, Q = diag of the 2x2 rotation per node
+    (isotropic material)."""
+    d = 3
+    n = 2 ** d
+    c, s = np.cos(np.pi / 6), np.sin(np.pi / 6)
+    C = fem.c_matrix(1.0, 0.3)
+    K0, M0 = fem.assemble_square(d, 0.0, 0.0, 1.0, C)
+    Kr, Mr = fem.assemble_square(d, 0.0, 0.0, 1.0, C, (c, s, -s, c))
+    R = np.array([[c, -s], [s, c]])
+    Q = np.kron(np.eye(n * n), R)
+    np.testing.assert_allclose(Kr.toarray(), Q @ K0.toarray() @ Q.T, atol=1e-13)
+    np.testing.assert_allclose(Mr.toarray(), M0.toarray(), atol=1e-15)
+
+
+def test_constant_traction_resultant():
+    """A uniform traction t on a side of length L has nodal loads summing to
+    t L (the cantilever strip's tip load: 3 on the unit-height end)."""
+    prob = W.cantilever_strip(3, q=2, traction=-3.0)
+    K, f, mask, info = fem.assemble_system(prob)
+    assert f[1::2].sum() == pytest.approx(-3.0, rel=1e-13)
+    assert abs(f[0::2].sum()) < 1e-14
+
+
+def test_cantilever_strip_tip_deflection_converges_to_beam_theory():
+    """The paper's cantilever beam (20 unit squares in a row, clamped end,
+    uniform end traction 3 on unit height, plane stress E = 64, nu = 0):
+    the mean tip deflection of the FEM solution approaches Timoshenko's
+    P L^3 / (3 E I) + P L / (k G A) = 1500 + 2.25 (P = 3, L = 20, I = 1/12,
+    G = 32, shear factor 5/6) as the level grows (Q1 bending converges
+    from below)."""
+    ref = 3.0 * 20.0 ** 3 / (3.0 * 64.0 / 12.0) + 3.0 * 20.0 / (5.0 / 6.0 * 32.0)
+    errs = []
+    for d in (2, 3, 4, 5):
+        prob = W.cantilever_strip(d)
+        u, _ = fem.solve_problem(prob, order="canonical")
+        n = 2 ** d
+        L = (n - 1) + n * np.arange(n)
+        tip = -u[1 + 2 * (L + n * n * (prob.q - 1))].mean()
+        errs.append(abs(tip - ref) / ref)
+    assert all(errs[i + 1] < errs[i] for i in range(3)), errs
+    assert errs[2] < 3e-3 and errs[3] < 1e-3, errs

@@ -150,3 +150,101 @@ def test_adam_two_steps_match_hand_computation():
                                                - 0.002663370379756864, abs=1e-14)
     assert params[0][1][0] == pytest.approx(0.5 + 0.009999999800000003
                                             - 0.006553266139001128, abs=1e-14)
+
+
+def _orthogonal(rng, r):
+    q, rr = np.linalg.qr(rng.standard_normal((r, r)))
+    return q * np.sign(np.diag(rr))
+
+
+def test_align_gauge_undoes_a_known_gauge_change():
+    """Insert random orthogonal G_k G_k^T at every bond of a train (same
+    tensor, other cores): aligning the result to the original recovers the
+    original cores exactly (the Procrustes optimum is the inverse rotation,
+    with zero residual), and the tensor never changes."""
+    rng = np.random.default_rng(5)
+    nrow = [2, 3, 2, 2, 4, 2]
+    ranks = W.capped_ranks(nrow, 5)
+    x = W.random_tt_cores(11, nrow, ranks)
+    y = [c.copy() for c in x]
+    for k in range(1, len(nrow)):
+        G = _orthogonal(rng, ranks[k])
+        y[k - 1] = np.tensordot(y[k - 1], G, axes=(2, 0))
+        y[k] = np.tensordot(G.T, y[k], axes=(1, 0))
+    assert max(np.abs(a - b).max() for a, b in zip(x, y)) > 0.1
+    z = WS.align_gauge(y, x)
+    assert max(np.abs(a - b).max() for a, b in zip(x, z)) <= 1e-12
+    assert np.abs(T.full_vector(z) - T.full_vector(y)).max() <= 1e-12 * np.abs(T.full_vector(y)).max()
+
+
+def test_align_gauge_minimises_the_core_distance():
+    """For two unrelated trains the aligned last core is closer to the
+    reference's than under any of 200 random orthogonal rotations (the
+    Procrustes optimality of each step), and the tensor is unchanged."""
+    rng = np.random.default_rng(6)
+    nrow = [2] * 6
+    ranks = W.capped_ranks(nrow, 4)
+    x = W.random_tt_cores(21, nrow, ranks)
+    ref = W.random_tt_cores(22, nrow, ranks)
+    z = WS.align_gauge(x, ref)
+    D = len(nrow)
+    best = np.linalg.norm(z[D - 1] - ref[D - 1])
+    r = ranks[D - 1]
+    for _ in range(200):
+        Q = _orthogonal(rng, r)
+        assert best <= np.linalg.norm(np.tensordot(Q.T, x[D - 1], axes=(1, 0)) - ref[D - 1]) + 1e-12
+    assert np.abs(T.full_vector(z) - T.full_vector(x)).max() <= 1e-12 * np.abs(T.full_vector(x)).max()
+
+
+def test_core_loss_gradient_matches_finite_differences():
+    rng = np.random.default_rng(7)
+    nrow, ranks, u = _setup(seed=3)
+    B = 3
+    targets = [u] + [W.random_tt_cores(40 + j, nrow, ranks) for j in range(B - 1)]
+    out = rng.standard_normal((WS.n_out(nrow, ranks), B))
+    loss, g = WS.batch_core_loss_grad(out, targets)
+    flat = [WS.flatten(t) for t in targets]
+    dense = np.mean([np.sum((out[:, j] - flat[j]) ** 2) / np.sum(flat[j] ** 2) for j in range(B)])
+    assert loss == pytest.approx(dense, rel=1e-13)
+    h = 1e-6
+    for (i, j) in [(0, 0), (5, 1), (WS.n_out(nrow, ranks) - 1, 2)]:
+        op, om = out.copy(), out.copy()
+        op[i, j] += h
+        om[i, j] -= h
+        fd = (WS.batch_core_loss_grad(op, targets)[0] - WS.batch_core_loss_grad(om, targets)[0]) / (2 * h)
+        assert g[i, j] == pytest.approx(fd, rel=1e-6, abs=1e-10)
+
+
+@pytest.mark.parametrize("metric", [False, True])
+def test_angle_loss_is_the_error_of_the_best_multiple(metric):
+    """The angle loss equals ||alpha x - u||^2 / ||u||^2 (dense, alpha the
+    least-squares multiple, in the Frobenius or the K norm), is unchanged by
+    scaling x, and its gradient matches finite differences."""
+    from oracle import assembly as A_
+    nrow, ranks, _ = _setup(seed=8, D=7, r=3)
+    A = None
+    if metric:
+        Kq, _ = A_.assemble_qtt(W.cantilever_traction(3))
+        A = Kq
+        nrow = [c.shape[1] for c in Kq]
+        ranks = W.capped_ranks(nrow, 3)
+    u = W.random_tt_cores(9, nrow, ranks)
+    o = np.random.default_rng(10).standard_normal(WS.n_out(nrow, ranks))
+    loss, g = WS.tt_angle_loss_grad(o, u, nrow, ranks, A)
+    xd = T.full_vector(WS.unflatten(o, nrow, ranks))
+    ud = T.full_vector(u)
+    M = T.full_matrix(A) if metric else np.eye(xd.size)
+    alpha = (xd @ M @ ud) / (xd @ M @ xd)
+    e = alpha * xd - ud
+    assert loss == pytest.approx((e @ M @ e) / (ud @ M @ ud), rel=1e-10)
+    o2 = o.copy()
+    o2[:nrow[0] * ranks[1]] *= -3.0          # scales the first core
+    assert WS.tt_angle_loss_grad(o2, u, nrow, ranks, A)[0] == pytest.approx(loss, rel=1e-10)
+    h = 1e-6
+    for i in [0, 7, WS.n_out(nrow, ranks) - 2]:
+        op, om = o.copy(), o.copy()
+        op[i] += h
+        om[i] -= h
+        fd = (WS.tt_angle_loss_grad(op, u, nrow, ranks, A)[0]
+              - WS.tt_angle_loss_grad(om, u, nrow, ranks, A)[0]) / (2 * h)
+        assert g[i] == pytest.approx(fd, rel=1e-5, abs=1e-9)

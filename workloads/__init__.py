@@ -24,7 +24,11 @@ WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
 
 @dataclass(frozen=True)
 class Square:
-    """One square subdomain [x0, x0+side] x [y0, y0+side].
+    """One square subdomain [x0, x0+side] x [y0, y0+side], or, with
+    ``edges = (ax, ay, bx, by)``, the parallelogram
+    {(x0, y0) + s (ax, ay) + t (bx, by) : s, t in [0, 1]} (``side`` is then
+    unused).  Nodes sit at s, t = i / (2^d - 1); the sides are numbered as
+    for the square (west s = 0, east s = 1, south t = 0, north t = 1).
 
     ``fixed[s][c]`` is True when component c (0 = x, 1 = y) is clamped on
     side s of this subdomain.
@@ -33,17 +37,26 @@ class Square:
     y0: float
     side: float
     fixed: Tuple[Tuple[bool, bool], ...] = ((False, False),) * 4
+    edges: Optional[Tuple[float, float, float, float]] = None
+
+    def edge_vectors(self):
+        """(a, b): the images of the unit vectors of the parameter square."""
+        if self.edges is None:
+            return (self.side, 0.0), (0.0, self.side)
+        ax, ay, bx, by = self.edges
+        return (ax, ay), (bx, by)
 
 
 @dataclass(frozen=True)
 class Traction:
-    """Traction t_comp(s) = sum_k amp[k-1] * sin(k*pi*s) on side ``side`` of
-    subdomain ``sub``; s in [0, 1] is the normalised arclength along the side
-    (x for south/north sides, y for west/east sides)."""
+    """Traction t_comp(s) = constant + sum_k amp[k-1] * sin(k*pi*s) on side
+    ``side`` of subdomain ``sub``; s in [0, 1] is the normalised arclength
+    along the side (x for south/north sides, y for west/east sides)."""
     sub: int
     side: int
     comp: int
     amp: Tuple[float, ...]
+    constant: float = 0.0
 
 
 @dataclass(frozen=True)
@@ -115,6 +128,30 @@ def l_shape(level: int, seed: int = 0, nmodes: int = 8) -> Problem:
     a = tuple(float(v) for v in traction_amplitudes(seed, nmodes))
     return Problem(level=level, subs=(s1, s2, s3),
                    tractions=(Traction(2, NORTH, 1, a),))
+
+
+def cantilever_strip(level: int, q: int = 20, traction: float = -3.0) -> Problem:
+    """The paper's cantilever beam (Sec. 5): q unit squares in a row
+    (length-to-height ratio q, 2^level nodes per subdomain side), the west
+    edge of the first clamped, a uniform vertical traction on the east edge
+    of the last (the free end); plane stress with E = 64 and nu = 0."""
+    clamp = ((True, True), (False, False), (False, False), (False, False))
+    free = ((False, False),) * 4
+    subs = tuple(Square(float(m), 0.0, 1.0, clamp if m == 0 else free) for m in range(q))
+    return Problem(level=level, subs=subs, E=64.0, nu=0.0, plane_strain=False,
+                   tractions=(Traction(q - 1, EAST, 1, (), float(traction)),))
+
+
+def skewed_cantilever(level: int, shear: float = 0.4, stretch: float = 1.3, seed: int = 0,
+                      nmodes: int = 8) -> Problem:
+    """A non-square subdomain: the parallelogram with edge vectors
+    a = (stretch, 0) and b = (shear, 1), its west side (s = 0) clamped and
+    the seeded sine traction of the cantilever workloads on its east side,
+    plane strain E = 1, nu = 0.3."""
+    clamp = ((True, True), (False, False), (False, False), (False, False))
+    sub = Square(0.0, 0.0, 1.0, clamp, edges=(float(stretch), 0.0, float(shear), 1.0))
+    a = tuple(float(v) for v in traction_amplitudes(seed, nmodes))
+    return Problem(level=level, subs=(sub,), tractions=(Traction(0, EAST, 1, a),))
 
 
 # ---------------------------------------------------------------- batched
