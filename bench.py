@@ -52,6 +52,8 @@ def _parse():
                     help="skip the level-5 and level-10 solve measurements")
     ap.add_argument("--batch", type=int, default=64,
                     help="cases of the batched-step measurement (0: skip)")
+    ap.add_argument("--batch-solves", type=int, default=256,
+                    help="cases of the batched-solve measurement (0: skip)")
     ap.add_argument("--learned", type=int, default=4096,
                     help="training targets of the learned warm start at level 10 (0: skip)")
     ap.add_argument("--learned-held", type=int, default=32,
@@ -235,37 +237,54 @@ def batched_steps(P, torch, ncases: int):
                 speedup_vs_1_worker=round(rates[1] / rates[best], 2))
 
 
-def batched_solves(P, torch, ncases: int):
+def batched_solves(P, torch, ncases: int, chunk: int = 32, ntune: int = 16):
     """Solves of the batched configuration: case i (rng(1000 + i)) draws its
     level (8..11), rank cap (16..96) and 16 load coefficients; each is solved
     by ALS (rank ramp from 16 to the cap, tol 1e-6, eps 1e-6, at most 24
     sweeps).  Cases run concurrently by host workers on their own streams
-    (qtt_solve_batched); solves/s at 1, 4 and 8 concurrent cases.  A case
-    whose cap is below the rank its solution needs stops at the sweep limit
-    (status QTT_E_NOCONV) with the best iterate of that rank."""
+    (qtt_solve_batched).  The worker count comes from the library's
+    autotuner (qtt_autotune_batched: 1, 2, 4, 8, 16 and 32 workers on the
+    first `ntune` cases, ranked by converged solves/s); then all `ncases`
+    run with it, `chunk` cases resident at a time (each case holds its own
+    workspace, up to 2.7 GB at level 11 and rank 96).  A case whose cap is
+    below the rank its solution needs stops at the sweep limit (status
+    QTT_E_NOCONV) with the best iterate of that rank: it is reported, and
+    not counted as a solve."""
     import workloads as W
-    probs = []
-    for i in range(ncases):
-        c = W.batch_case(i)
-        K, f = P.assemble(W.cantilever_two_component(c.level, c.coeffs))
-        opts = P.SolveOpts(tol=1e-6, eps=1e-6, rmax=c.cap, rmax_in=16, maxit_out=24,
-                           method="als", seed=1)
-        probs.append((K, f, opts))
-    batch = P.Batch(probs)
-    rates, res = {}, None
-    for conc in (1, 4, 8):
+
+    def problems(lo, hi):
+        out = []
+        for i in range(lo, hi):
+            c = W.batch_case(i)
+            K, f = P.assemble(W.cantilever_two_component(c.level, c.coeffs))
+            opts = P.SolveOpts(tol=1e-6, eps=1e-6, rmax=c.cap, rmax_in=16, maxit_out=24,
+                               method="als", seed=1)
+            out.append((K, f, opts))
+        return out
+
+    tune = P.Batch(problems(0, min(ntune, ncases)))
+    best, rates = P.autotune_batched(tune)
+    del tune
+    total, converged, noconv, sweeps = 0.0, 0, 0, []
+    for lo in range(0, ncases, chunk):
+        batch = P.Batch(problems(lo, min(lo + chunk, ncases)))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = P.solve_batched(batch, conc)
+        res = P.solve_batched(batch, best)
         torch.cuda.synchronize()
-        rates[conc] = time.perf_counter() - t0
-    best = min(rates, key=rates.get)
+        total += time.perf_counter() - t0
+        converged += sum(1 for _, r in res if r["status"] == 0)
+        noconv += sum(1 for _, r in res if r["status"] == -4)
+        sweeps += [r["outer"] for _, r in res]
+        del batch, res
     return dict(cases=ncases, levels=sorted(set(W.batch_case(i).level for i in range(ncases))),
-                caps=[W.batch_case(i).cap for i in range(ncases)],
-                solves_per_s={str(k): round(ncases / v, 3) for k, v in rates.items()},
-                best_concurrency=best, speedup_vs_1=round(rates[1] / rates[best], 2),
-                converged=sum(1 for _, r in res if r["status"] == 0),
-                sweeps=[r["outer"] for _, r in res])
+                caps_range=[min(W.batch_case(i).cap for i in range(ncases)),
+                            max(W.batch_case(i).cap for i in range(ncases))],
+                autotune_cases=min(ntune, ncases), best_concurrency=best,
+                autotune_converged_solves_per_s={str(k): round(v, 3) for k, v in rates.items()},
+                seconds=round(total, 2), converged=converged, stopped_at_sweep_limit=noconv,
+                converged_solves_per_s=round(converged / total, 3),
+                mean_sweeps=round(sum(sweeps) / len(sweeps), 2))
 
 
 def small_solve(P, torch, level: int, method: str):
@@ -504,7 +523,8 @@ def main():
                                share_of_step=round(sqr_ms / args.steps / (1e3 * dt), 3))
     mixed = mixed_precision(P, torch, K, x, ws, max(2, args.steps // 2))
     batched = batched_steps(P, torch, args.batch) if args.batch > 0 else None
-    bsolves = batched_solves(P, torch, 16) if (args.batch > 0 and args.solve) else None
+    bsolves = (batched_solves(P, torch, args.batch_solves)
+               if (args.batch_solves > 0 and args.solve) else None)
     solve5 = small_solve(P, torch, 5, "als") if args.solve else None
     solve5_fcg = small_solve(P, torch, 5, "fcg") if args.solve else None
     solve10 = level10_solve(P, torch, args.level) if args.solve else None

@@ -57,15 +57,25 @@ typedef enum {
 
 typedef enum { QTT_F64 = 0, QTT_F32 = 1, QTT_BF16 = 2 } qtt_dtype;
 
-/* A tensor train in caller-owned memory.  `ncol == NULL` marks a vector. */
+/* A tensor train in caller-owned memory (the TT/QTT format of Sec. 4:
+ * core k holds r_k x n_k (x m_k) x r_{k+1} values, column-major with the
+ * left rank fastest, cores packed one after another).  `ncol == NULL` marks
+ * a vector. */
 typedef struct {
   int32_t ncores;
-  const int32_t *nrow;   /* host, ncores mode sizes                         */
-  const int32_t *ncol;   /* host, ncores column mode sizes, or NULL         */
+  const int32_t *nrow;   /* host, ncores mode sizes (1..64)                 */
+  const int32_t *ncol;   /* host, ncores column mode sizes (1..64), or NULL */
   int32_t *ranks;        /* host, ncores + 1 ranks; inputs read them,
                             producers write them                           */
   double *data;          /* device, packed cores                            */
-  int64_t capacity;      /* number of doubles available at `data`           */
+  int64_t capacity;      /* number of values available at `data`            */
+  int32_t *d_ranks;      /* optional device mirror of ranks (ncores + 1
+                            int32 in device memory, or NULL): producers
+                            also write the ranks there, on their stream    */
+  qtt_dtype dtype;       /* storage type of `data`: QTT_F64 (the only one
+                            this library stores; others are refused with
+                            QTT_E_UNSUPPORTED).  Low-precision arithmetic is
+                            chosen per call by its `compute` argument.     */
 } qtt_tt;
 
 /* ------------------------------------------------------------ problem
@@ -101,12 +111,18 @@ typedef struct {
   double body[2];           /* constant body force                          */
   int32_t ntrac;
   const qtt_traction *trac;
-  int32_t coupling;         /* q > 1: 0 = symmetric exact coupling (copy
-                               averaging plus copy Laplacian), 1 = the
-                               paper's coupling rows (Sec. 3.6.1); the
-                               latter is not symmetric and is for assembly
-                               only                                        */
+  int32_t coupling;         /* q > 1: QTT_COUPLING_PAPER (0), the paper's
+                               coupling rows (Sec. 3.6.1; not symmetric, for
+                               assembly only), or QTT_COUPLING_SYMMETRIC
+                               (1), the symmetric exact coupling (copy
+                               averaging plus copy Laplacian) that the
+                               solvers take                                */
+  double gamma;             /* q > 1: the coupling penalty; <= 0 selects the
+                               paper's choice, the mean diagonal of one
+                               subdomain's stiffness (Sec. 3.6.1)          */
 } qtt_problem;
+
+enum { QTT_COUPLING_PAPER = 0, QTT_COUPLING_SYMMETRIC = 1 };
 
 /* qtt_assemble_stiffness — Alg. 1: global stiffness K and load f in
  * Z-ordered QTT form after coupling and Dirichlet conditions.

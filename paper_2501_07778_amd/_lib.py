@@ -26,7 +26,8 @@ class QttError(RuntimeError):
 class _TT(C.Structure):
     _fields_ = [("ncores", C.c_int32), ("nrow", C.POINTER(C.c_int32)),
                 ("ncol", C.POINTER(C.c_int32)), ("ranks", C.POINTER(C.c_int32)),
-                ("data", C.c_void_p), ("capacity", C.c_int64)]
+                ("data", C.c_void_p), ("capacity", C.c_int64),
+                ("d_ranks", C.c_void_p), ("dtype", C.c_int32)]
 
 
 class _Square(C.Structure):
@@ -44,7 +45,8 @@ class _Problem(C.Structure):
     _fields_ = [("level", C.c_int32), ("q", C.c_int32), ("sub", C.POINTER(_Square)),
                 ("E", C.c_double), ("nu", C.c_double), ("plane_strain", C.c_int32),
                 ("body", C.c_double * 2), ("ntrac", C.c_int32),
-                ("trac", C.POINTER(_Traction)), ("coupling", C.c_int32)]
+                ("trac", C.POINTER(_Traction)), ("coupling", C.c_int32),
+                ("gamma", C.c_double)]
 
 
 class _SolveOpts(C.Structure):
@@ -433,7 +435,7 @@ def problem_from_workload(p, coupling: str = "symmetric") -> Problem:
     keep.append(trs)
     c = _Problem(p.level, len(p.subs), subs, p.E, p.nu, 1 if p.plane_strain else 0,
                  (C.c_double * 2)(*p.body), len(p.tractions), trs,
-                 1 if coupling == "paper" else 0)
+                 0 if coupling == "paper" else 1, 0.0)
     return Problem(c, keep)
 
 
@@ -441,9 +443,11 @@ def qtt_modes(level: int, q: int) -> List[int]:
     return [2] + ([q] if q > 1 else []) + [2] * (2 * level)
 
 
-def assemble(p, coupling: str = "symmetric", eps: float = 1e-14):
-    """qtt_assemble_stiffness: returns (K, f) as device TTs."""
+def assemble(p, coupling: str = "symmetric", eps: float = 1e-14, gamma: float = 0.0):
+    """qtt_assemble_stiffness: returns (K, f) as device TTs (gamma <= 0:
+    the paper's coupling penalty)."""
     prob = problem_from_workload(p, coupling)
+    prob.c.gamma = float(gamma)
     wsb, kc, fc = C.c_size_t(), C.c_int64(), C.c_int64()
     _check(lib().qtt_assemble_workspace(C.byref(prob.c), C.byref(wsb), C.byref(kc), C.byref(fc)))
     modes = qtt_modes(p.level, len(p.subs))

@@ -556,6 +556,7 @@ qtt_status solve_als(const qtt_tt *K, const qtt_tt *f, const qtt_tt *xin,
     mr = std::max(mr, (int)ur[k]);
   }
   R.max_rank = mr;
+  QTT_HIP(publish_ranks(u, s));
   R.status = converged ? QTT_OK : QTT_E_NOCONV;
   R.warm_start = warm;
   R.warm_energy = xin ? x0_energy : 0.0;

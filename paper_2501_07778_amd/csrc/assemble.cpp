@@ -704,9 +704,10 @@ bool coupled(const Geometry &g, Rounder &rd, HTT &K, HTT &f) {
   Geometry g1 = g;
   g1.q = 1;
   HTT Ksq = block_stiffness(g1, rd);
-  const double gamma = trace(Ksq) / (2.0 * std::ldexp(1.0, 2 * g.d));
+  const double gamma =
+      g.p->gamma > 0.0 ? g.p->gamma : trace(Ksq) / (2.0 * std::ldexp(1.0, 2 * g.d));
   HTT I = identity_like(K);
-  if (g.p->coupling == 1) {
+  if (g.p->coupling == QTT_COUPLING_PAPER) {
     std::vector<const HTT *> pp;
     std::vector<double> pc;
     for (auto &t : P) {
@@ -798,7 +799,9 @@ qtt_status check_problem(const qtt_problem *p) {
         t.nmodes < 0 || (t.nmodes > 0 && !t.amp))
       return fail(QTT_E_INVAL, "bad traction entry");
   }
-  if (p->coupling != 0 && p->coupling != 1) return fail(QTT_E_INVAL, "coupling must be 0 or 1");
+  if (p->coupling != QTT_COUPLING_PAPER && p->coupling != QTT_COUPLING_SYMMETRIC)
+    return fail(QTT_E_INVAL, "coupling must be QTT_COUPLING_PAPER or QTT_COUPLING_SYMMETRIC");
+  if (!(p->gamma == p->gamma)) return fail(QTT_E_INVAL, "gamma is NaN");
   return QTT_OK;
 }
 
@@ -1043,6 +1046,7 @@ extern "C" qtt_status qtt_assemble_stiffness(const qtt_problem *p, double eps, q
       off += (int64_t)t.c[k].size();
     }
     for (int k = 0; k <= D; ++k) o->ranks[k] = t.r[k];
+    QTT_HIP(publish_ranks(o, rd.s));
     return QTT_OK;
   };
   if ((st = put(Kbc, K, "K")) != QTT_OK) return st;
@@ -1110,6 +1114,7 @@ extern "C" qtt_status qtt_assemble_bpx(const qtt_problem *p, double eps, qtt_tt 
     off += (int64_t)Cbc.c[k].size();
   }
   for (int k = 0; k <= D; ++k) C->ranks[k] = Cbc.r[k];
+  QTT_HIP(publish_ranks(C, rd.s));
   QTT_HIP(hipStreamSynchronize(rd.s));
   return QTT_OK;
 }

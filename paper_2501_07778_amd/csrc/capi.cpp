@@ -62,6 +62,8 @@ bool arena_tt(Arena &ar, TTDesc &t, int D, const int32_t *n,
 // ---------------------------------------------------------------- checks
 qtt_status check_tt(const qtt_tt *t, const char *name, bool need_ranks) {
   if (!t) return fail(QTT_E_INVAL, std::string(name) + " is NULL");
+  if (t->dtype != QTT_F64)
+    return fail(QTT_E_UNSUPPORTED, std::string(name) + ": storage dtype must be QTT_F64");
   if (t->ncores < 1 || t->ncores > QTT_MAX_CORES)
     return fail(QTT_E_INVAL, std::string(name) + ": ncores out of range");
   if (!t->nrow || !t->ranks)
@@ -87,6 +89,13 @@ qtt_status check_tt(const qtt_tt *t, const char *name, bool need_ranks) {
     if (!t->data) return fail(QTT_E_INVAL, std::string(name) + ": NULL data");
   }
   return QTT_OK;
+}
+
+// the device mirror of a producer's ranks, when the caller keeps one
+hipError_t publish_ranks(const qtt_tt *t, hipStream_t s) {
+  if (!t || !t->d_ranks) return hipSuccess;
+  return hipMemcpyAsync(t->d_ranks, t->ranks, sizeof(int32_t) * (t->ncores + 1),
+                        hipMemcpyHostToDevice, s);
 }
 
 int64_t packed_elems(const qtt_tt *t) {
@@ -166,6 +175,7 @@ qtt_status qtt_matvec(const qtt_tt *A, const qtt_tt *x, qtt_tt *y,
   QTT_HIP(upload_ranks(va, A->ranks, s));
   QTT_HIP(upload_ranks(vx, x->ranks, s));
   QTT_HIP(launch_matvec(va, vx, vy, compute, s));
+  QTT_HIP(publish_ranks(y, s));
   return QTT_OK;
 }
 
@@ -223,6 +233,7 @@ qtt_status qtt_round(qtt_tt *x, double eps, int32_t rmax, double *norm,
   QTT_HIP(hipMemcpyAsync(scal, w.scal, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
   QTT_HIP(hipStreamSynchronize(s));
   for (int k = 0; k <= x->ncores; ++k) x->ranks[k] = rk_host[k];
+  QTT_HIP(publish_ranks(x, s));
   if (norm) *norm = scal[0];
   if (err) *err = std::sqrt(scal[1] > 0.0 ? scal[1] : 0.0);
   return QTT_OK;
@@ -280,6 +291,7 @@ qtt_status qtt_round_sketch(qtt_tt *x, int32_t ell, uint64_t seed, double eps, i
   QTT_HIP(hipMemcpyAsync(scal, w.scal, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
   QTT_HIP(hipStreamSynchronize(s));
   for (int k = 0; k <= x->ncores; ++k) x->ranks[k] = rk_host[k];
+  QTT_HIP(publish_ranks(x, s));
   if (norm) *norm = scal[0];
   if (err) *err = std::sqrt(scal[1] > 0.0 ? scal[1] : 0.0);
   return QTT_OK;
@@ -384,6 +396,7 @@ qtt_status qtt_matvec_round(const qtt_tt *A, const qtt_tt *x, qtt_tt *y, qtt_dty
   QTT_HIP(launch_pack(t.v, (double *)y->data, s));
   QTT_HIP(hipStreamSynchronize(s));
   for (int k = 0; k <= D; ++k) y->ranks[k] = rk_host[k];
+  QTT_HIP(publish_ranks(y, s));
   if (norm) *norm = scal[0];
   if (err) *err = std::sqrt(scal[1] > 0.0 ? scal[1] : 0.0);
   return QTT_OK;
@@ -455,6 +468,7 @@ qtt_status qtt_axpby(double a, const qtt_tt *x, double b, const qtt_tt *y,
   QTT_HIP(upload_ranks(vx, x->ranks, s));
   QTT_HIP(upload_ranks(vy, y->ranks, s));
   QTT_HIP(launch_axpby(a, nullptr, vx, b, nullptr, vy, vz, s));
+  QTT_HIP(publish_ranks(z, s));
   return QTT_OK;
 }
 

@@ -244,6 +244,7 @@ extern "C" qtt_status qtt_tt_contract_last(const qtt_tt *x, const double *w, qtt
   QTT_HIP(hipGetLastError());
   for (int k = 0; k < D - 1; ++k) y->ranks[k] = x->ranks[k];
   y->ranks[D - 1] = 1;
+  QTT_HIP(publish_ranks(y, s));
   return QTT_OK;
 }
 
@@ -343,5 +344,6 @@ extern "C" qtt_status qtt_tt_combine(int32_t nterms, const double *coeffs, const
     QTT_HIP(hipGetLastError());
     for (int k = 1; k < D; ++k) off[k] += x[i]->ranks[k];
   }
+  QTT_HIP(publish_ranks(z, s));
   return QTT_OK;
 }

@@ -43,6 +43,7 @@ qtt_status fail(qtt_status st, const std::string &msg);
 // need_ranks also boundary ranks 1, interior ranks in range, capacity for
 // the packed cores and non-NULL data.
 qtt_status check_tt(const qtt_tt *t, const char *name, bool need_ranks);
+hipError_t publish_ranks(const qtt_tt *t, hipStream_t s);
 #define QTT_HIP(call)                                                     \
   do {                                                                    \
     hipError_t e_ = (call);                                               \

@@ -979,5 +979,6 @@ extern "C" qtt_status qtt_warmstart_infer_tt(const qtt_mlp *net, const float *a,
                      dim3(256), 0, s, w.H[net->nlayers], x0->data, (int64_t)nout);
   QTT_HIP(hipGetLastError());
   for (int k = 0; k <= ncores; ++k) x0->ranks[k] = ranks[k];
+  QTT_HIP(publish_ranks(x0, s));
   return QTT_OK;
 }

@@ -16,6 +16,7 @@
 // steps of one core run in one workgroup; the GEMMs of absorb and fold use
 // the whole chip.
 #include "dev_gemm.h"
+#include "dev_reduce.h"
 #include "internal.h"
 
 namespace qtt {
@@ -31,14 +32,13 @@ constexpr int NGRP = WG / GL;
 // its second factor) in 150 KiB of LDS
 constexpr int LDS_DBL = 19200;
 constexpr int LDS_TAU = 160;       // min(rows, cols) <= sqrt(LDS_DBL)
-// the SVD step keeps nothing else in LDS, so its array can take 159 KiB
-constexpr int LDS_SVD = 20352;
+// the SVD step keeps nothing else in LDS but the Jacobi column norms, so its
+// array can take 157.5 KiB
+constexpr int LDS_SVD = 20160;
+constexpr int JNRM = 160;          // columns whose squared norms the Jacobi tracks
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+// sums over a wavefront (every lane active): DPP row moves, dev_reduce.h
+__device__ __forceinline__ double wave_sum(double v) { return dev::wave64_sum(v); }
 
 // block-wide sum; `red` holds NWAVE doubles of LDS
 __device__ double block_sum(double v, double *red) {
@@ -265,10 +265,10 @@ __global__ void __launch_bounds__(WG)
   if (threadIdx.x == 0) scal[0] = sqrt(p);
 }
 
+// Sum over the 16 lanes of a group (GL = 16: a group is one DPP row).
 __device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int o = GL / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GL);
-  return v;
+  static_assert(GL == 16, "group_sum reduces one 16-lane DPP row");
+  return dev::row16_sum(v);
 }
 
 // One-sided Jacobi (Hestenes) on the columns of B (mb x nb, ld = mb) with V
@@ -277,8 +277,16 @@ __device__ __forceinline__ double group_sum(double v) {
 // pair.  A pair is rotated while |b_p . b_q| > tol ||b_p|| ||b_q||; since V
 // stays orthogonal, B_in = (B V) V^T holds whatever tol is, and columns
 // dropped later contribute exactly their norms to the truncation error.
+// Up to JNRM columns the squared norms are computed once per sweep and then
+// carried through the rotations (the rotation that zeroes b_p . b_q = g with
+// tangent t maps them to al - t g and be + t g, as in Hestenes' method), so
+// a pair needs one reduction instead of three; a norm that the update would
+// shrink below a quarter is recomputed.  The norms only steer the angles:
+// every rotation is exact, so B V V^T = B_in holds regardless.
 __device__ int jacobi(double *B, int mb, int nb, double *V, double *rot_log, int *flag,
                       double tol) {
+  __shared__ double cn[JNRM];
+  const bool track = nb <= JNRM;
   const int gl = threadIdx.x % GL, grp = threadIdx.x / GL;
   if (V)
     for (int64_t e = threadIdx.x; e < (int64_t)nb * nb; e += WG)
@@ -288,6 +296,15 @@ __device__ int jacobi(double *B, int mb, int nb, double *V, double *rot_log, int
   for (int sweep = 0; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
     __syncthreads();
     if (threadIdx.x == 0) *flag = 0;
+    if (track) {
+      for (int j = grp; j < nb; j += NGRP) {
+        const double *bj = B + (int64_t)mb * j;
+        double sacc = 0.0;
+        for (int l = gl; l < mb; l += GL) sacc = fma(bj[l], bj[l], sacc);
+        sacc = group_sum(sacc);
+        if (gl == 0) cn[j] = sacc;
+      }
+    }
     __syncthreads();
     for (int r = 0; r < N - 1; ++r) {
       double *lg = rot_log ? rot_log + 2 * ((int64_t)(sweep * (N - 1) + r) * (N / 2)) : nullptr;
@@ -300,17 +317,27 @@ __device__ int jacobi(double *B, int mb, int nb, double *V, double *rot_log, int
         if (p > q) { int t = p; p = q; q = t; }
         double *bp = B + (int64_t)mb * (act ? p : 0), *bq = B + (int64_t)mb * (act ? q : 0);
         double al = 0.0, be = 0.0, ga = 0.0;
-        if (act) {
-          for (int l = gl; l < mb; l += GL) {
-            const double u = bp[l], v = bq[l];
-            al = fma(u, u, al);
-            be = fma(v, v, be);
-            ga = fma(u, v, ga);
+        if (track) {
+          if (act)
+            for (int l = gl; l < mb; l += GL) ga = fma(bp[l], bq[l], ga);
+          ga = group_sum(ga);
+          if (act) {
+            al = cn[p];
+            be = cn[q];
           }
+        } else {
+          if (act) {
+            for (int l = gl; l < mb; l += GL) {
+              const double u = bp[l], v = bq[l];
+              al = fma(u, u, al);
+              be = fma(v, v, be);
+              ga = fma(u, v, ga);
+            }
+          }
+          al = group_sum(al);
+          be = group_sum(be);
+          ga = group_sum(ga);
         }
-        al = group_sum(al);
-        be = group_sum(be);
-        ga = group_sum(ga);
         double c = 1.0, sn = 0.0;
         if (act && ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
           const double zeta = (be - al) / (2.0 * ga);
@@ -321,10 +348,26 @@ __device__ int jacobi(double *B, int mb, int nb, double *V, double *rot_log, int
             t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           c = 1.0 / sqrt(1.0 + t * t);
           sn = c * t;
+          double np = 0.0, nq = 0.0;
           for (int l = gl; l < mb; l += GL) {
             const double u = bp[l], v = bq[l];
-            bp[l] = c * u - sn * v;
-            bq[l] = sn * u + c * v;
+            const double u2 = c * u - sn * v, v2 = sn * u + c * v;
+            bp[l] = u2;
+            bq[l] = v2;
+            np = fma(u2, u2, np);
+            nq = fma(v2, v2, nq);
+          }
+          if (track) {
+            double ap = al - t * ga, aq = be + t * ga;
+            // cancellation: measure instead (uniform over the group)
+            if (!(ap >= 0.25 * al) || !(aq >= 0.25 * be)) {
+              ap = group_sum(np);
+              aq = group_sum(nq);
+            }
+            if (gl == 0) {
+              cn[p] = ap;
+              cn[q] = aq;
+            }
           }
           if (V) {
             double *vp = V + (int64_t)nb * p, *vq = V + (int64_t)nb * q;

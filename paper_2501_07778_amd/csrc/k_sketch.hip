@@ -21,6 +21,7 @@
 #include <cstdlib>
 
 #include "dev_gemm.h"
+#include "dev_reduce.h"
 #include "internal.h"
 
 namespace qtt {
@@ -172,11 +173,8 @@ __global__ void k_splitk_reduce(const int64_t *dims, const double *P, double *C)
   }
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+// sums over a wavefront (every lane active): DPP row moves, dev_reduce.h
+__device__ __forceinline__ double wave_sum(double v) { return dev::wave64_sum(v); }
 
 __device__ double block_sum(double v, double *red) {
   v = wave_sum(v);

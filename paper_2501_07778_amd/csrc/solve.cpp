@@ -671,6 +671,7 @@ extern "C" qtt_status qtt_solve(const qtt_tt *K, const qtt_tt *f, const qtt_tt *
     mr = rkh[k] > mr ? rkh[k] : mr;
   }
   R.max_rank = mr;
+  QTT_HIP(publish_ranks(u, s));
   R.status = converged ? QTT_OK : QTT_E_NOCONV;
   R.warm_start = x0 ? 1 : 0;
   if (rep) *rep = R;

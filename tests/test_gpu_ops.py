@@ -307,3 +307,26 @@ def test_dot_wide_operands_against_oracle(P):
     ref = T.dot(x, y)
     got = P.dot(P.tt_from_cores(x), P.tt_from_cores(y))
     assert got == pytest.approx(ref, rel=1e-11, abs=1e-12 * T.norm(x) * T.norm(y))
+
+
+def test_device_rank_mirror_and_explicit_gamma(P):
+    """A producer writes its ranks to the caller's device mirror (d_ranks)
+    too; an explicit coupling penalty equal to the paper's default gives the
+    same operator, another one a different operator."""
+    import torch
+    K, f = P.assemble(W.cantilever_traction(4))
+    x = P.tt_from_cores(W.random_tt_cores(3, K.nrow, W.capped_ranks(K.nrow, 5)))
+    dr = torch.full((K.D + 1,), -1, dtype=torch.int32, device="cuda")
+    y = P.matvec(K, x)
+    y.c.d_ranks = dr.data_ptr()
+    P.round_(y, 1e-6, 4)
+    torch.cuda.synchronize()
+    assert dr.cpu().tolist() == y.ranks
+    prob = W.l_shape(3)
+    K1, _ = P.assemble(prob)
+    from oracle import fem
+    Kd, _, _, info = fem.assemble_system(prob)
+    for gamma, same in ((info["gamma"], True), (3.0 * info["gamma"], False)):
+        K2, _ = P.assemble(prob, gamma=gamma)
+        d = np.abs(T.full_matrix(P.tt_to_cores(K1)) - T.full_matrix(P.tt_to_cores(K2))).max()
+        assert (d <= 1e-12) == same, (gamma, d)

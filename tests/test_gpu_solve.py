@@ -363,16 +363,18 @@ def test_assembly_of_parallelogram_and_strip_matches_sparse_fem(P, d, which):
     np.testing.assert_allclose(T.full_vector(P.tt_to_cores(ft)), fz, atol=1e-12 * np.abs(fz).max())
 
 
-@pytest.mark.parametrize("which,d,rmax,bound", [("skewed", 5, 64, 1e-9), ("strip", 3, 128, 1e-7),
+@pytest.mark.parametrize("which,d,rmax,bound", [("skewed", 5, 64, 1e-9), ("strip", 3, 128, 3e-7),
                                                  ("strip", 5, 64, 2e-5)])
 def test_solve_parallelogram_and_strip_against_direct(P, which, d, rmax, bound):
     """The parallelogram subdomain by ALS at full rank (the mode-product
     bounds): the oracle's sparse direct solve to 1e-9.  The cantilever
     strip (20 squares in a row, aspect ratio 20) by AMEn: its conditioning
-    puts a floor under the per-sweep change (near 5e-8 at level 3 and 2e-6
-    at level 5, 40,960 dofs, where one-site ALS at rank 48 stalls too), so
-    the stop tolerances are 1e-7 and 3e-6 and the errors against the direct
-    solve 1e-7 and 2e-5 (measured 2.0e-8 in 8 sweeps and 3.9e-6 in 12)."""
+    puts a floor under the per-sweep change (between 5e-8 and 1.5e-7 at
+    level 3, depending on the rounding's last bits, and near 2e-6 at level
+    5, 40,960 dofs, where one-site ALS at rank 48 stalls too), so the stop
+    tolerances are 3e-7 and 3e-6 and the errors against the direct solve
+    3e-7 and 2e-5 (measured 2e-8 to 3e-8 in 8 sweeps and 3.4e-6 to 3.9e-6
+    in 12 to 14)."""
     prob = W.skewed_cantilever(d) if which == "skewed" else W.cantilever_strip(d)
     uref, _ = fem.solve_problem(prob)
     K, f = P.assemble(prob)
@@ -380,7 +382,7 @@ def test_solve_parallelogram_and_strip_against_direct(P, which, d, rmax, bound):
         opts = P.SolveOpts(tol=1e-10, eps=0.0, rmax=rmax, maxit_out=30, rmax_in=0, method="als",
                            seed=1)
     else:
-        opts = P.SolveOpts(tol=1e-7 if d == 3 else 3e-6, eps=1e-10, rmax=rmax, rmax_in=8,
+        opts = P.SolveOpts(tol=3e-7 if d == 3 else 3e-6, eps=1e-10, rmax=rmax, rmax_in=8,
                            eps_in=1e-2, maxit_out=80, method="amen", seed=1)
     print("solve %s d=%d rank %d" % (which, d, rmax), flush=True)
     u, rep = P.solve(K, f, opts)

@@ -57,7 +57,32 @@ def test_host_validation_without_gpu():
     assert L.qtt_round_workspace(C.byref(t), 0, C.byref(need)) == 0 and need.value > 0
     # a workspace that is too small is reported, not used
     assert L.qtt_round(C.byref(t), 1e-8, 0, None, None, None, 16, None) == -3
+    # storage other than FP64 is refused before any launch
+    t.dtype = 1
+    assert L.qtt_round(C.byref(t), 1e-8, 0, None, None, None, 16, None) == -7
+    assert b"dtype" in L.qtt_last_error()
+    t.dtype = 0
     assert L.qtt_version().startswith(b"qtt")
+
+
+def test_problem_coupling_and_gamma_validation():
+    """The coupling field takes QTT_COUPLING_PAPER (0) or
+    QTT_COUPLING_SYMMETRIC (1); a NaN gamma is refused (host checks only)."""
+    if not os.path.exists(LIB):
+        pytest.skip("libqtt.so not built")
+    import paper_2501_07778_amd as P
+    import workloads as W
+    L = P.lib()
+    prob = P._lib.problem_from_workload(W.l_shape(3))
+    assert prob.c.coupling == 1 and prob.c.gamma == 0.0
+    need, kc, fc = C.c_size_t(), C.c_int64(), C.c_int64()
+    assert L.qtt_assemble_workspace(C.byref(prob.c), C.byref(need), C.byref(kc), C.byref(fc)) == 0
+    prob.c.coupling = 2
+    assert L.qtt_assemble_workspace(C.byref(prob.c), C.byref(need), C.byref(kc), C.byref(fc)) == -1
+    prob.c.coupling = 0
+    prob.c.gamma = float("nan")
+    assert L.qtt_assemble_workspace(C.byref(prob.c), C.byref(need), C.byref(kc), C.byref(fc)) == -1
+    assert b"gamma" in L.qtt_last_error()
 
 
 def test_als_options_and_workspace_on_the_host():
