@@ -44,3 +44,59 @@ __device__ __forceinline__ double wave64_sum(double v) {
 
 }  // namespace dev
 }  // namespace qtt
+
+namespace qtt {
+namespace dev {
+
+constexpr int REFL_REG = 4;   // reflector elements per lane held in registers
+
+// Apply the Householder reflector H = I - t v v^T, v = [1 at row j; wj below
+// it] (wj is the reflector's column, rows long), to the columns c0 <= c < c1
+// of Y (leading dimension ldy), one wavefront per column, NW wavefronts.
+// When the reflector has at most 64 REFL_REG entries below row j each lane
+// keeps its part of it in registers and reads each column once, so a column
+// costs one wait for memory instead of two.
+template <int NW>
+__device__ __forceinline__ void reflect_cols(const double *wj, int j, int rows, double t,
+                                             double *Y, int64_t ldy, int c0, int c1) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (rows - (j + 1) <= 64 * REFL_REG) {
+    double wv[REFL_REG];
+#pragma unroll
+    for (int k = 0; k < REFL_REG; ++k) {
+      const int i = j + 1 + lane + 64 * k;
+      wv[k] = i < rows ? wj[i] : 0.0;
+    }
+    for (int c = c0 + wave; c < c1; c += NW) {
+      double *yc = Y + ldy * c;
+      double yv[REFL_REG];
+#pragma unroll
+      for (int k = 0; k < REFL_REG; ++k) {
+        const int i = j + 1 + lane + 64 * k;
+        yv[k] = i < rows ? yc[i] : 0.0;
+      }
+      double s = (lane == 0) ? yc[j] : 0.0;
+#pragma unroll
+      for (int k = 0; k < REFL_REG; ++k) s = fma(wv[k], yv[k], s);
+      s = wave64_sum(s) * t;
+      if (lane == 0) yc[j] -= s;
+#pragma unroll
+      for (int k = 0; k < REFL_REG; ++k) {
+        const int i = j + 1 + lane + 64 * k;
+        if (i < rows) yc[i] = yv[k] - s * wv[k];
+      }
+    }
+    return;
+  }
+  for (int c = c0 + wave; c < c1; c += NW) {
+    double *yc = Y + ldy * c;
+    double s = (lane == 0) ? yc[j] : 0.0;
+    for (int i = j + 1 + lane; i < rows; i += 64) s += wj[i] * yc[i];
+    s = wave64_sum(s) * t;
+    if (lane == 0) yc[j] -= s;
+    for (int i = j + 1 + lane; i < rows; i += 64) yc[i] -= s * wj[i];
+  }
+}
+
+}  // namespace dev
+}  // namespace qtt

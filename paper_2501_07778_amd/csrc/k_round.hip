@@ -33,9 +33,10 @@ constexpr int NGRP = WG / GL;
 constexpr int LDS_DBL = 19200;
 constexpr int LDS_TAU = 160;       // min(rows, cols) <= sqrt(LDS_DBL)
 // the SVD step keeps nothing else in LDS but the Jacobi column norms, so its
-// array can take 157.5 KiB
-constexpr int LDS_SVD = 20160;
+// array can take 156 KiB
+constexpr int LDS_SVD = 20000;
 constexpr int JNRM = 160;          // columns whose squared norms the Jacobi tracks
+constexpr int JB = 5;              // column elements per lane kept in registers (<= 80 rows)
 
 // sums over a wavefront (every lane active): DPP row moves, dev_reduce.h
 __device__ __forceinline__ double wave_sum(double v) { return dev::wave64_sum(v); }
@@ -119,16 +120,7 @@ __device__ void householder_qr(double *W, int rows, int cols, double *tau,
       tau[j] = t;
     }
     __syncthreads();
-    if (t != 0.0) {
-      for (int c = j + 1 + wave; c < cols; c += NWAVE) {
-        double *wc = W + (int64_t)rows * c;
-        double s = (lane == 0) ? wc[j] : 0.0;
-        for (int i = j + 1 + lane; i < rows; i += 64) s += wj[i] * wc[i];
-        s = wave_sum(s) * t;
-        if (lane == 0) wc[j] -= s;
-        for (int i = j + 1 + lane; i < rows; i += 64) wc[i] -= s * wj[i];
-      }
-    }
+    if (t != 0.0) dev::reflect_cols<NWAVE>(wj, j, rows, t, W, rows, j + 1, cols);
     __syncthreads();
   }
 }
@@ -144,17 +136,7 @@ __device__ void form_q(const double *W, int rows, int kq, const double *tau,
   __syncthreads();
   for (int j = kq - 1; j >= 0; --j) {
     const double t = tau[j];
-    if (t != 0.0) {
-      const double *wj = W + (int64_t)rows * j;
-      for (int c = j + wave; c < kq; c += NWAVE) {
-        double *qc = Q + (int64_t)rows * c;
-        double s = (lane == 0) ? qc[j] : 0.0;
-        for (int i = j + 1 + lane; i < rows; i += 64) s += wj[i] * qc[i];
-        s = wave_sum(s) * t;
-        if (lane == 0) qc[j] -= s;
-        for (int i = j + 1 + lane; i < rows; i += 64) qc[i] -= s * wj[i];
-      }
-    }
+    if (t != 0.0) dev::reflect_cols<NWAVE>(W + (int64_t)rows * j, j, rows, t, Q, rows, j, kq);
     __syncthreads();
   }
 }
@@ -166,17 +148,7 @@ __device__ void apply_q(const double *W, int rows, int kq, const double *tau, do
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int j = kq - 1; j >= 0; --j) {
     const double t = tau[j];
-    if (t != 0.0) {
-      const double *wj = W + (int64_t)rows * j;
-      for (int c = wave; c < ncols; c += NWAVE) {
-        double *yc = Y + (int64_t)rows * c;
-        double s = (lane == 0) ? yc[j] : 0.0;
-        for (int i = j + 1 + lane; i < rows; i += 64) s += wj[i] * yc[i];
-        s = wave_sum(s) * t;
-        if (lane == 0) yc[j] -= s;
-        for (int i = j + 1 + lane; i < rows; i += 64) yc[i] -= s * wj[i];
-      }
-    }
+    if (t != 0.0) dev::reflect_cols<NWAVE>(W + (int64_t)rows * j, j, rows, t, Y, rows, 0, ncols);
     __syncthreads();
   }
 }
@@ -283,10 +255,12 @@ __device__ __forceinline__ double group_sum(double v) {
 // a pair needs one reduction instead of three; a norm that the update would
 // shrink below a quarter is recomputed.  The norms only steer the angles:
 // every rotation is exact, so B V V^T = B_in holds regardless.
+template <bool REG>
 __device__ int jacobi(double *B, int mb, int nb, double *V, double *rot_log, int *flag,
                       double tol) {
   __shared__ double cn[JNRM];
   const bool track = nb <= JNRM;
+  const bool breg = REG && track && mb <= GL * JB;
   const int gl = threadIdx.x % GL, grp = threadIdx.x / GL;
   if (V)
     for (int64_t e = threadIdx.x; e < (int64_t)nb * nb; e += WG)
@@ -317,7 +291,24 @@ __device__ int jacobi(double *B, int mb, int nb, double *V, double *rot_log, int
         if (p > q) { int t = p; p = q; q = t; }
         double *bp = B + (int64_t)mb * (act ? p : 0), *bq = B + (int64_t)mb * (act ? q : 0);
         double al = 0.0, be = 0.0, ga = 0.0;
-        if (track) {
+        // short columns stay in registers from the dot product to the rotation
+        double ur[JB], wr[JB];
+        if (breg) {
+#pragma unroll
+          for (int k = 0; k < JB; ++k) {
+            const int l = gl + GL * k;
+            const bool in = act && l < mb;
+            ur[k] = in ? bp[l] : 0.0;
+            wr[k] = in ? bq[l] : 0.0;
+          }
+#pragma unroll
+          for (int k = 0; k < JB; ++k) ga = fma(ur[k], wr[k], ga);
+          ga = group_sum(ga);
+          if (act) {
+            al = cn[p];
+            be = cn[q];
+          }
+        } else if (track) {
           if (act)
             for (int l = gl; l < mb; l += GL) ga = fma(bp[l], bq[l], ga);
           ga = group_sum(ga);
@@ -349,13 +340,27 @@ __device__ int jacobi(double *B, int mb, int nb, double *V, double *rot_log, int
           c = 1.0 / sqrt(1.0 + t * t);
           sn = c * t;
           double np = 0.0, nq = 0.0;
-          for (int l = gl; l < mb; l += GL) {
-            const double u = bp[l], v = bq[l];
-            const double u2 = c * u - sn * v, v2 = sn * u + c * v;
-            bp[l] = u2;
-            bq[l] = v2;
-            np = fma(u2, u2, np);
-            nq = fma(v2, v2, nq);
+          if (breg) {
+#pragma unroll
+            for (int k = 0; k < JB; ++k) {
+              const int l = gl + GL * k;
+              const double u2 = c * ur[k] - sn * wr[k], v2 = sn * ur[k] + c * wr[k];
+              if (l < mb) {
+                bp[l] = u2;
+                bq[l] = v2;
+              }
+              np = fma(u2, u2, np);
+              nq = fma(v2, v2, nq);
+            }
+          } else {
+            for (int l = gl; l < mb; l += GL) {
+              const double u = bp[l], v = bq[l];
+              const double u2 = c * u - sn * v, v2 = sn * u + c * v;
+              bp[l] = u2;
+              bq[l] = v2;
+              np = fma(u2, u2, np);
+              nq = fma(v2, v2, nq);
+            }
           }
           if (track) {
             double ap = al - t * ga, aq = be + t * ga;
@@ -547,7 +552,7 @@ __global__ void __launch_bounds__(WG)
       X[e] = (j <= i) ? Bq[j + (int64_t)mb * i] : 0.0;  // X[i, j] = R[j, i]
     }
     __syncthreads();
-    jacobi(X, nb, nb, Vv, nullptr, &flag, jacobi_tol(eps, nb));
+    jacobi<true>(X, nb, nb, Vv, nullptr, &flag, jacobi_tol(eps, nb));
     const int rank = truncate_rank(X, nb, nb, sig, w.perm, delta0, rmax, scal, &rank_s);
     if (threadIdx.x == 0) w.fr[k] = rank;
     // F = kept columns of W (r0 x rank); Y = Q [V_kept; 0] (nc x rank)
@@ -583,7 +588,7 @@ __global__ void __launch_bounds__(WG)
   __syncthreads();
   // tall: the kept core is V^T, orthogonal for any stopping tolerance; wide:
   // it is built from the columns of B V, which must be orthogonal to FP64
-  const int sweeps = jacobi(B, mb, nb, V, replay ? rot_log : nullptr, &flag,
+  const int sweeps = jacobi<false>(B, mb, nb, V, replay ? rot_log : nullptr, &flag,
                             jacobi_tol(tall ? eps : 0.0, mb));
   const double delta = (D > 1) ? eps * scal[0] / sqrt((double)(D - 1)) : 0.0;
   const int rank = truncate_rank(B, mb, nb, sig, w.perm, delta, rmax, scal, &rank_s);

@@ -225,16 +225,7 @@ __global__ void __launch_bounds__(WG) k_sketch_qr(const double *S, int rows, int
       tau[j] = t;
     }
     __syncthreads();
-    if (t != 0.0) {
-      for (int c = j + 1 + wave; c < cols; c += NWAVE) {
-        double *wc = W + rows * c;
-        double s = (lane == 0) ? wc[j] : 0.0;
-        for (int i = j + 1 + lane; i < rows; i += 64) s += wj[i] * wc[i];
-        s = wave_sum(s) * t;
-        if (lane == 0) wc[j] -= s;
-        for (int i = j + 1 + lane; i < rows; i += 64) wc[i] -= s * wj[i];
-      }
-    }
+    if (t != 0.0) dev::reflect_cols<NWAVE>(wj, j, rows, t, W, rows, j + 1, cols);
     __syncthreads();
   }
   double *Q = q_lds ? W + rows * cols : gw + rows * cols;
@@ -242,17 +233,7 @@ __global__ void __launch_bounds__(WG) k_sketch_qr(const double *S, int rows, int
   __syncthreads();
   for (int j = kmax - 1; j >= 0; --j) {
     const double t = tau[j];
-    if (t != 0.0) {
-      const double *wj = W + rows * j;
-      for (int c = j + wave; c < kmax; c += NWAVE) {
-        double *qc = Q + rows * c;
-        double s = (lane == 0) ? qc[j] : 0.0;
-        for (int i = j + 1 + lane; i < rows; i += 64) s += wj[i] * qc[i];
-        s = wave_sum(s) * t;
-        if (lane == 0) qc[j] -= s;
-        for (int i = j + 1 + lane; i < rows; i += 64) qc[i] -= s * wj[i];
-      }
-    }
+    if (t != 0.0) dev::reflect_cols<NWAVE>(W + rows * j, j, rows, t, Q, rows, j, kmax);
     __syncthreads();
   }
   for (int e = threadIdx.x; e < rows * kmax; e += WG) Qout[e] = Q[e];
