@@ -55,6 +55,67 @@ __device__ void gemm_tile(const double *A, int lda, const double *B, int ldb, do
     }
 }
 
+typedef double dbl4_t __attribute__((ext_vector_type(4)));
+constexpr int MK = 32;   // depth staged per step of the matrix-core tile
+
+// The same 64 x 64 output tile on the FP64 matrix cores: each of the four
+// wavefronts owns a 32 x 32 quarter as 2 x 2 blocks of
+// v_mfma_f64_16x16x4f64 (A operand: lane l holds row l%16 at depth l/16;
+// B operand likewise for the column; result element v of lane l is row
+// l/16 + 4v of column l%16).  Depth is staged through LDS in steps of MK,
+// loaded so that consecutive threads read consecutive addresses.
+template <bool TA>
+__device__ void gemm_tile_mfma(const double *A, int lda, const double *B, int ldb, double *C,
+                               int ldc, int M, int N, int K, int tm, int tn) {
+  __shared__ double As[GT][MK + 1];
+  __shared__ double Bs[GT][MK + 1];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int rr = lane & 15, kq = lane >> 4;
+  const int m0 = tm * GT, n0 = tn * GT;
+  dbl4_t acc00 = {0.0, 0.0, 0.0, 0.0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
+  for (int k0 = 0; k0 < K; k0 += MK) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < GT * MK; e += 256) {
+      int mm, kk;
+      if (TA) {
+        kk = e % MK;
+        mm = e / MK;
+      } else {
+        mm = e % GT;
+        kk = e / GT;
+      }
+      const int gm = m0 + mm, gk = k0 + kk;
+      double av = 0.0;
+      if (gm < M && gk < K) av = TA ? A[gk + (int64_t)lda * gm] : A[gm + (int64_t)lda * gk];
+      As[mm][kk] = av;
+      const int kb = e % MK, nn = e / MK;
+      const int gn = n0 + nn, gkb = k0 + kb;
+      Bs[nn][kb] = (gkb < K && gn < N) ? B[gkb + (int64_t)ldb * gn] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < MK; kk += 4) {
+      const double a0 = As[wr + rr][kk + kq], a1 = As[wr + 16 + rr][kk + kq];
+      const double b0 = Bs[wc + rr][kk + kq], b1 = Bs[wc + 16 + rr][kk + kq];
+      acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
+      acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
+      acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
+      acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
+    }
+  }
+  const dbl4_t accs[2][2] = {{acc00, acc01}, {acc10, acc11}};
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gm = m0 + wr + 16 * bi + kq + 4 * v, gn = n0 + wc + 16 * bj + rr;
+        if (gm < M && gn < N) C[gm + (int64_t)ldc * gn] = accs[bi][bj][v];
+      }
+}
+
 // Split-K variant: block z handles the K range [z*kc, (z+1)*kc) and writes
 // its partial product to P + z*ldc*N (ldc = M); the partials are summed by
 // splitk_reduce.  Thin products (few output tiles, long K) need this to keep
@@ -76,7 +137,7 @@ __device__ void gemm_tile_k(const double *A, int lda, const double *B, int ldb, 
     return;
   }
   const double *Ak = TA ? A + k0 : A + (int64_t)lda * k0;
-  gemm_tile<TA>(Ak, lda, B + k0, ldb, P + (int64_t)z * M * N, M, M, N, kk, tm, tn);
+  gemm_tile_mfma<TA>(Ak, lda, B + k0, ldb, P + (int64_t)z * M * N, M, M, N, kk, tm, tn);
 }
 
 }  // namespace dev
