@@ -49,41 +49,58 @@ namespace qtt {
 namespace dev {
 
 constexpr int REFL_REG = 4;   // reflector elements per lane held in registers
+constexpr int REFL_U = 2;     // columns per wavefront in flight at once
 
-// Apply the Householder reflector H = I - t v v^T, v = [1 at row j; wj below
-// it] (wj is the reflector's column, rows long), to the columns c0 <= c < c1
-// of Y (leading dimension ldy), one wavefront per column, NW wavefronts.
-// When the reflector has at most 64 REFL_REG entries below row j each lane
-// keeps its part of it in registers and reads each column once, so a column
-// costs one wait for memory instead of two.
+// Apply the Householder reflector H = I - t v v^T, v = [1 at row j; vs * wj
+// below it] (wj is the reflector's column, rows long, and vs a factor the
+// caller has not yet applied to it), to the columns c0 <= c < c1 of Y
+// (leading dimension ldy), one wavefront per column, NW wavefronts.  When
+// the reflector has at most 64 REFL_REG entries below row j each lane keeps
+// its part in registers and a wavefront works on REFL_U columns at once
+// (their loads, dot products and sums overlap), so a column costs a share
+// of one memory wait and one reduction latency.
 template <int NW>
-__device__ __forceinline__ void reflect_cols(const double *wj, int j, int rows, double t,
-                                             double *Y, int64_t ldy, int c0, int c1) {
+__device__ __forceinline__ void reflect_cols(const double *wj, int j, int rows, double vs,
+                                             double t, double *Y, int64_t ldy, int c0, int c1) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (rows - (j + 1) <= 64 * REFL_REG) {
+    // rows past the end read row j instead (in bounds) with a zero weight
+    int iv[REFL_REG];
+    bool ok[REFL_REG];
     double wv[REFL_REG];
 #pragma unroll
     for (int k = 0; k < REFL_REG; ++k) {
       const int i = j + 1 + lane + 64 * k;
-      wv[k] = i < rows ? wj[i] : 0.0;
+      ok[k] = i < rows;
+      iv[k] = ok[k] ? i : j;
+      const double w = wj[iv[k]];
+      wv[k] = ok[k] ? vs * w : 0.0;
     }
-    for (int c = c0 + wave; c < c1; c += NW) {
-      double *yc = Y + ldy * c;
-      double yv[REFL_REG];
+    for (int cb = c0 + wave; cb < c1; cb += NW * REFL_U) {
+      double yv[REFL_U][REFL_REG], s[REFL_U];
 #pragma unroll
-      for (int k = 0; k < REFL_REG; ++k) {
-        const int i = j + 1 + lane + 64 * k;
-        yv[k] = i < rows ? yc[i] : 0.0;
+      for (int u = 0; u < REFL_U; ++u) {
+        const int c = cb + NW * u;
+        const double *yc = Y + ldy * (c < c1 ? c : cb);
+        const double y0 = yc[j];
+        s[u] = (lane == 0) ? y0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < REFL_REG; ++k) yv[u][k] = yc[iv[k]];
+#pragma unroll
+        for (int k = 0; k < REFL_REG; ++k) s[u] = fma(wv[k], yv[u][k], s[u]);
       }
-      double s = (lane == 0) ? yc[j] : 0.0;
 #pragma unroll
-      for (int k = 0; k < REFL_REG; ++k) s = fma(wv[k], yv[k], s);
-      s = wave64_sum(s) * t;
-      if (lane == 0) yc[j] -= s;
+      for (int u = 0; u < REFL_U; ++u) s[u] = wave64_sum(s[u]) * t;
 #pragma unroll
-      for (int k = 0; k < REFL_REG; ++k) {
-        const int i = j + 1 + lane + 64 * k;
-        if (i < rows) yc[i] = yv[k] - s * wv[k];
+      for (int u = 0; u < REFL_U; ++u) {
+        const int c = cb + NW * u;
+        if (c < c1) {
+          double *yc = Y + ldy * c;
+          if (lane == 0) yc[j] -= s[u];
+#pragma unroll
+          for (int k = 0; k < REFL_REG; ++k)
+            if (ok[k]) yc[iv[k]] = yv[u][k] - s[u] * wv[k];
+        }
       }
     }
     return;
@@ -91,10 +108,10 @@ __device__ __forceinline__ void reflect_cols(const double *wj, int j, int rows, 
   for (int c = c0 + wave; c < c1; c += NW) {
     double *yc = Y + ldy * c;
     double s = (lane == 0) ? yc[j] : 0.0;
-    for (int i = j + 1 + lane; i < rows; i += 64) s += wj[i] * yc[i];
+    for (int i = j + 1 + lane; i < rows; i += 64) s = fma(vs * wj[i], yc[i], s);
     s = wave64_sum(s) * t;
     if (lane == 0) yc[j] -= s;
-    for (int i = j + 1 + lane; i < rows; i += 64) yc[i] -= s * wj[i];
+    for (int i = j + 1 + lane; i < rows; i += 64) yc[i] -= s * (vs * wj[i]);
   }
 }
 

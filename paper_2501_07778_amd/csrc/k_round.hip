@@ -16,6 +16,7 @@
 // steps of one core run in one workgroup; the GEMMs of absorb and fold use
 // the whole chip.
 #include "dev_gemm.h"
+#include "dev_qr.h"
 #include "dev_reduce.h"
 #include "internal.h"
 
@@ -35,8 +36,8 @@ constexpr int LDS_TAU = 160;       // min(rows, cols) <= sqrt(LDS_DBL)
 // the SVD step keeps nothing else in LDS but the Jacobi column norms, so its
 // array can take 156 KiB
 constexpr int LDS_SVD = 20000;
+constexpr int YREG = 13;          // Y elements per thread staged in registers (wide SVD step)
 constexpr int JNRM = 160;          // columns whose squared norms the Jacobi tracks
-constexpr int JB = 5;              // column elements per lane kept in registers (<= 80 rows)
 
 // sums over a wavefront (every lane active): DPP row moves, dev_reduce.h
 __device__ __forceinline__ double wave_sum(double v) { return dev::wave64_sum(v); }
@@ -92,66 +93,11 @@ __global__ void k_last_to_carry(TTView x, double *carry) {
     carry[e] = c[e];
 }
 
-// Householder QR of a column-major rows x cols matrix W (ld = rows) in
-// place: R above the diagonal, reflectors below, tau[j].  LAPACK-style
-// reflectors H = I - tau v v^T with v(0) = 1.
-__device__ void householder_qr(double *W, int rows, int cols, double *tau,
-                               double *red) {
-  const int kmax = rows < cols ? rows : cols;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int j = 0; j < kmax; ++j) {
-    double *wj = W + (int64_t)rows * j;
-    double p = 0.0;
-    for (int i = j + 1 + threadIdx.x; i < rows; i += WG) p += wj[i] * wj[i];
-    const double xnorm2 = block_sum(p, red);
-    const double alpha = wj[j];
-    double t = 0.0, beta = alpha, scale = 0.0;
-    if (xnorm2 > 0.0) {
-      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-      t = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    __syncthreads();
-    if (t != 0.0) {
-      for (int i = j + 1 + threadIdx.x; i < rows; i += WG) wj[i] *= scale;
-    }
-    if (threadIdx.x == 0) {
-      wj[j] = beta;
-      tau[j] = t;
-    }
-    __syncthreads();
-    if (t != 0.0) dev::reflect_cols<NWAVE>(wj, j, rows, t, W, rows, j + 1, cols);
-    __syncthreads();
-  }
-}
-
-// Q (rows x kq, ld = rows) = H_0 ... H_{kq-1} [I; 0] from the reflectors in W.
-__device__ void form_q(const double *W, int rows, int kq, const double *tau,
-                       double *Q) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int64_t e = threadIdx.x; e < (int64_t)rows * kq; e += WG) {
-    const int i = (int)(e % rows), c = (int)(e / rows);
-    Q[e] = (i == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int j = kq - 1; j >= 0; --j) {
-    const double t = tau[j];
-    if (t != 0.0) dev::reflect_cols<NWAVE>(W + (int64_t)rows * j, j, rows, t, Q, rows, j, kq);
-    __syncthreads();
-  }
-}
-
-// Y (rows x ncols, ld = rows) <- H_0 H_1 ... H_{kq-1} Y with the reflectors
-// stored below the diagonal of W (householder_qr layout)
-__device__ void apply_q(const double *W, int rows, int kq, const double *tau, double *Y,
-                        int ncols) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int j = kq - 1; j >= 0; --j) {
-    const double t = tau[j];
-    if (t != 0.0) dev::reflect_cols<NWAVE>(W + (int64_t)rows * j, j, rows, t, Y, rows, 0, ncols);
-    __syncthreads();
-  }
-}
+// Householder QR, Q and products with Q: dev_qr.h (LAPACK's reflector
+// convention, one workgroup barrier per column)
+using dev::apply_q;
+using dev::form_q_inplace;
+using dev::householder_qr;
 
 // Left sweep, core k: QR of the left unfolding (rows = nr[k]*nm_k,
 // cols = rk[k+1]); Q -> slot k, R -> rbuf (ld = r'), nr[k+1] = r'.  The LDS
@@ -160,7 +106,6 @@ template <bool LDS>
 __global__ void __launch_bounds__(WG)
     k_qr_step(TTView x, int k, const double *src, double *work, double *rbuf,
               double *tau_g, int *iwork) {
-  __shared__ double red[NWAVE];
   __shared__ double lds[LDS ? LDS_DBL : 1];
   __shared__ double tau_l[LDS ? LDS_TAU : 1];
   IW w = iw_of(iwork, x.D);
@@ -170,25 +115,20 @@ __global__ void __launch_bounds__(WG)
   const int rq = rows < cols ? rows : cols;
   if (w.nr[k] > x.cap[k] || cols > x.cap[k + 1]) return;  // ranks beyond the slots
   const bool use_lds = LDS && (int64_t)rows * cols <= LDS_DBL && rq <= LDS_TAU;
-  const bool q_lds = use_lds && (int64_t)rows * cols + (int64_t)rows * rq <= LDS_DBL;
   double *W = use_lds ? lds : work;
   double *tau = use_lds ? tau_l : tau_g;
   for (int64_t e = threadIdx.x; e < (int64_t)rows * cols; e += WG) W[e] = src[e];
   __syncthreads();
-  householder_qr(W, rows, cols, tau, red);
+  householder_qr<NWAVE>(W, rows, cols, tau);
   // R: rq x cols, upper trapezoid
   for (int64_t e = threadIdx.x; e < (int64_t)rq * cols; e += WG) {
     const int i = (int)(e % rq), c = (int)(e / rq);
     rbuf[e] = (i <= c) ? W[i + (int64_t)rows * c] : 0.0;
   }
+  // Q in place of the reflectors, then out to slot k
+  form_q_inplace<NWAVE>(W, rows, rq, tau);
   double *slot = x.data + x.off[k];
-  if (q_lds) {
-    double *Q = lds + (int64_t)rows * cols;
-    form_q(W, rows, rq, tau, Q);
-    for (int64_t e = threadIdx.x; e < (int64_t)rows * rq; e += WG) slot[e] = Q[e];
-  } else {
-    form_q(W, rows, rq, tau, slot);
-  }
+  for (int64_t e = threadIdx.x; e < (int64_t)rows * rq; e += WG) slot[e] = W[e];
   if (threadIdx.x == 0) w.nr[k + 1] = rq;
 }
 
@@ -243,6 +183,53 @@ __device__ __forceinline__ double group_sum(double v) {
   return dev::row16_sum(v);
 }
 
+// Reciprocal and reciprocal square root from the hardware estimates
+// (v_rcp_f64, v_rsq_f64) and two Newton steps each, which take them to
+// about one ulp; for the positive normal arguments of the rotations below.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
+// The Jacobi rotation of a column pair with squared norms al, be and inner
+// product ga: rotate when |ga| > tol sqrt(al be) (tested with the hardware
+// reciprocal square root estimates: the threshold needs no precision);
+// then zeta = (be - al) / (2 ga), t = sign(zeta) / (|zeta| + sqrt(1 +
+// zeta^2)) (the smaller root of t^2 + 2 zeta t - 1 = 0), c = 1 / sqrt(1 +
+// t^2), s = c t.  Only c must be accurate (c^2 + s^2 = 1 to rounding
+// whatever t is), so the chain uses the refined estimates above; |zeta|
+// beyond 5e149 gives t = 1 / (2 zeta) and a ga below 1e-290 the IEEE chain.
+__device__ __forceinline__ bool jac_angle(double al, double be, double ga, double tol, double &c,
+                                          double &sn, double &t) {
+  if (!(ga != 0.0 &&
+        fabs(ga) * (__builtin_amdgcn_rsq(al) * __builtin_amdgcn_rsq(be)) > tol))
+    return false;
+  const double d = be - al;
+  if (fabs(d) > 1e150 * fabs(ga)) {
+    t = ga / d;
+  } else if (fabs(ga) >= 1e-290) {
+    const double zeta = 0.5 * d * rcp_nr(ga);
+    const double h = fma(zeta, zeta, 1.0);
+    t = copysign(rcp_nr(fabs(zeta) + h * rsq_nr(h)), zeta >= 0.0 ? 1.0 : -1.0);
+  } else {
+    const double zeta = d / (2.0 * ga);
+    t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  }
+  c = rsq_nr(fma(t, t, 1.0));
+  sn = c * t;
+  return true;
+}
+
 // One-sided Jacobi (Hestenes) on the columns of B (mb x nb, ld = mb) with V
 // (nb x nb) accumulated: B V has mutually orthogonal columns.  Round-robin
 // ordering: each round pairs all columns disjointly, one 16-lane group per
@@ -255,12 +242,10 @@ __device__ __forceinline__ double group_sum(double v) {
 // a pair needs one reduction instead of three; a norm that the update would
 // shrink below a quarter is recomputed.  The norms only steer the angles:
 // every rotation is exact, so B V V^T = B_in holds regardless.
-template <bool REG>
 __device__ int jacobi(double *B, int mb, int nb, double *V, double *rot_log, int *flag,
                       double tol) {
   __shared__ double cn[JNRM];
   const bool track = nb <= JNRM;
-  const bool breg = REG && track && mb <= GL * JB;
   const int gl = threadIdx.x % GL, grp = threadIdx.x / GL;
   if (V)
     for (int64_t e = threadIdx.x; e < (int64_t)nb * nb; e += WG)
@@ -291,24 +276,7 @@ __device__ int jacobi(double *B, int mb, int nb, double *V, double *rot_log, int
         if (p > q) { int t = p; p = q; q = t; }
         double *bp = B + (int64_t)mb * (act ? p : 0), *bq = B + (int64_t)mb * (act ? q : 0);
         double al = 0.0, be = 0.0, ga = 0.0;
-        // short columns stay in registers from the dot product to the rotation
-        double ur[JB], wr[JB];
-        if (breg) {
-#pragma unroll
-          for (int k = 0; k < JB; ++k) {
-            const int l = gl + GL * k;
-            const bool in = act && l < mb;
-            ur[k] = in ? bp[l] : 0.0;
-            wr[k] = in ? bq[l] : 0.0;
-          }
-#pragma unroll
-          for (int k = 0; k < JB; ++k) ga = fma(ur[k], wr[k], ga);
-          ga = group_sum(ga);
-          if (act) {
-            al = cn[p];
-            be = cn[q];
-          }
-        } else if (track) {
+        if (track) {
           if (act)
             for (int l = gl; l < mb; l += GL) ga = fma(bp[l], bq[l], ga);
           ga = group_sum(ga);
@@ -329,38 +297,16 @@ __device__ int jacobi(double *B, int mb, int nb, double *V, double *rot_log, int
           be = group_sum(be);
           ga = group_sum(ga);
         }
-        double c = 1.0, sn = 0.0;
-        if (act && ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          double t;
-          if (fabs(zeta) > 1e150)
-            t = 0.5 / zeta;
-          else
-            t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          c = 1.0 / sqrt(1.0 + t * t);
-          sn = c * t;
+        double c = 1.0, sn = 0.0, t = 0.0;
+        if (act && jac_angle(al, be, ga, tol, c, sn, t)) {
           double np = 0.0, nq = 0.0;
-          if (breg) {
-#pragma unroll
-            for (int k = 0; k < JB; ++k) {
-              const int l = gl + GL * k;
-              const double u2 = c * ur[k] - sn * wr[k], v2 = sn * ur[k] + c * wr[k];
-              if (l < mb) {
-                bp[l] = u2;
-                bq[l] = v2;
-              }
-              np = fma(u2, u2, np);
-              nq = fma(v2, v2, nq);
-            }
-          } else {
-            for (int l = gl; l < mb; l += GL) {
-              const double u = bp[l], v = bq[l];
-              const double u2 = c * u - sn * v, v2 = sn * u + c * v;
-              bp[l] = u2;
-              bq[l] = v2;
-              np = fma(u2, u2, np);
-              nq = fma(v2, v2, nq);
-            }
+          for (int l = gl; l < mb; l += GL) {
+            const double u = bp[l], v = bq[l];
+            const double u2 = c * u - sn * v, v2 = sn * u + c * v;
+            bp[l] = u2;
+            bq[l] = v2;
+            np = fma(u2, u2, np);
+            nq = fma(v2, v2, nq);
           }
           if (track) {
             double ap = al - t * ga, aq = be + t * ga;
@@ -393,6 +339,169 @@ __device__ int jacobi(double *B, int mb, int nb, double *V, double *rot_log, int
     }
     sweeps = sweep + 1;
     __syncthreads();
+    if (*flag == 0) break;
+  }
+  __syncthreads();
+  return sweeps;
+}
+
+// One Jacobi rotation of the column pair (xp, xq) held by a 16-lane group
+// (K rows per lane) together with the same columns of V (vp, vq); al and be
+// are the columns' squared norms, carried through the rotation.  The test
+// and the angle are those of jacobi(); every value is uniform over the
+// group.  Returns whether the pair was rotated.
+template <int K>
+__device__ __forceinline__ bool jac_pair(double (&xp)[K], double (&xq)[K], double (&vp)[K],
+                                         double (&vq)[K], double &al, double &be, bool act,
+                                         double tol) {
+  double ga = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) ga = fma(xp[k], xq[k], ga);
+  ga = group_sum(ga);
+  double c, sn, t;
+  if (!(act && jac_angle(al, be, ga, tol, c, sn, t))) return false;
+  double np = 0.0, nq = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double u = xp[k], v = xq[k];
+    xp[k] = c * u - sn * v;
+    xq[k] = sn * u + c * v;
+    np = fma(xp[k], xp[k], np);
+    nq = fma(xq[k], xq[k], nq);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double u = vp[k], v = vq[k];
+    vp[k] = c * u - sn * v;
+    vq[k] = sn * u + c * v;
+  }
+  double ap = al - t * ga, aq = be + t * ga;
+  if (!(ap >= 0.25 * al) || !(aq >= 0.25 * be)) {
+    ap = group_sum(np);
+    aq = group_sum(nq);
+  }
+  al = ap;
+  be = aq;
+  return true;
+}
+
+// exchange of a group's column (registers of B and V, norm and index) with
+// the group whose lanes differ in bit 4 (MASK 16) or bit 5 (MASK 32)
+template <int K, int MASK>
+__device__ __forceinline__ void jac_swap(double (&x)[K], double (&v)[K], double &nrm, int &col) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    x[k] = __shfl_xor(x[k], MASK);
+    v[k] = __shfl_xor(v[k], MASK);
+  }
+  nrm = __shfl_xor(nrm, MASK);
+  col = __shfl_xor(col, MASK);
+}
+
+// Block-cyclic one-sided Jacobi on B (mb x nb, ld mb) with V (nb x nb, ld
+// nb) accumulated, for mb, nb <= 16 K; the result has the properties stated
+// for jacobi().  The columns form blocks of four.  The blocks meet in
+// round-robin order, one block pair per wavefront and a workgroup barrier
+// per block round; within a pair each 16-lane group holds one column of
+// each block, and of V, in registers (rows gl + 16 k).  The four pairings
+// of the two blocks' columns take four inner rounds, between which the
+// second block's columns pass to another group by lane exchanges (bit 4,
+// bit 5, bit 4 of the lane index), so the inner rounds touch no LDS.  The
+// six pairs inside each block are rotated in the first block round of each
+// sweep (three rounds, two pairs per block).  Every column pair is visited
+// once per sweep, as in the cyclic order.
+template <int K>
+__device__ int jacobi_blk(double *B, int mb, int nb, double *V, int *flag, double tol) {
+  const int gl = threadIdx.x & 15, g = (threadIdx.x >> 4) & 3, wave = threadIdx.x >> 6;
+  for (int64_t e = threadIdx.x; e < (int64_t)nb * nb; e += WG)
+    V[e] = ((e % nb) == (e / nb)) ? 1.0 : 0.0;
+  const int nblk = (nb + 3) / 4, NB = nblk + (nblk & 1);
+  auto load = [&](double (&x)[K], double (&v)[K], int c) {
+    const bool in = c < nb;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int l = gl + GL * k;
+      x[k] = (in && l < mb) ? B[l + (int64_t)mb * c] : 0.0;
+      v[k] = (in && l < nb) ? V[l + (int64_t)nb * c] : 0.0;
+    }
+  };
+  auto store = [&](const double (&x)[K], const double (&v)[K], int c) {
+    if (c >= nb) return;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int l = gl + GL * k;
+      if (l < mb) B[l + (int64_t)mb * c] = x[k];
+      if (l < nb) V[l + (int64_t)nb * c] = v[k];
+    }
+  };
+  auto sqnorm = [&](const double (&x)[K]) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) s = fma(x[k], x[k], s);
+    return group_sum(s);
+  };
+  int sweeps = 0;
+  for (int sweep = 0; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
+    __syncthreads();
+    if (threadIdx.x == 0) *flag = 0;
+    __syncthreads();
+    bool rotated = false;
+    for (int r = 0; r < NB - 1; ++r) {
+      for (int i = wave; i < NB / 2; i += NWAVE) {
+        int a = (r + i) % (NB - 1);
+        int b = (i == 0) ? (NB - 1) : (r - i + NB - 1) % (NB - 1);
+        if (a > b) { const int t = a; a = b; b = t; }
+        double xp[K], xq[K], vp[K], vq[K];
+        if (r == 0) {
+          // pairs inside blocks a (groups 0, 1) and b (groups 2, 3): (0,1)
+          // (2,3), then (0,2) (1,3), then (0,3) (1,2)
+          const int h = g & 1, base = 4 * ((g < 2) ? a : b);
+          int cp = base + 2 * h, cq = cp + 1;
+          load(xp, vp, cp);
+          load(xq, vq, cq);
+          double al = sqnorm(xp), be = sqnorm(xq);
+          rotated |= jac_pair<K>(xp, xq, vp, vq, al, be, cq < nb, tol);
+          // group h = 0 passes its second column, h = 1 its first
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const double xr = __shfl_xor(h ? xp[k] : xq[k], 16);
+            const double vr = __shfl_xor(h ? vp[k] : vq[k], 16);
+            if (h) { xp[k] = xr; vp[k] = vr; } else { xq[k] = xr; vq[k] = vr; }
+          }
+          {
+            const double nr = __shfl_xor(h ? al : be, 16);
+            const int cr = __shfl_xor(h ? cp : cq, 16);
+            if (h) { al = nr; cp = cr; } else { be = nr; cq = cr; }
+          }
+          rotated |= jac_pair<K>(xp, xq, vp, vq, al, be, cp < nb && cq < nb, tol);
+          jac_swap<K, 16>(xq, vq, be, cq);
+          rotated |= jac_pair<K>(xp, xq, vp, vq, al, be, cp < nb && cq < nb, tol);
+          store(xp, vp, cp);
+          store(xq, vq, cq);
+          // the same wavefront reads these columns back below (in order)
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
+        if (b < nblk) {
+          int cp = 4 * a + g, cq = 4 * b + g;
+          load(xp, vp, cp);
+          load(xq, vq, cq);
+          double al = sqnorm(xp), be = sqnorm(xq);
+          rotated |= jac_pair<K>(xp, xq, vp, vq, al, be, cp < nb && cq < nb, tol);
+          jac_swap<K, 16>(xq, vq, be, cq);
+          rotated |= jac_pair<K>(xp, xq, vp, vq, al, be, cp < nb && cq < nb, tol);
+          jac_swap<K, 32>(xq, vq, be, cq);
+          rotated |= jac_pair<K>(xp, xq, vp, vq, al, be, cp < nb && cq < nb, tol);
+          jac_swap<K, 16>(xq, vq, be, cq);
+          rotated |= jac_pair<K>(xp, xq, vp, vq, al, be, cp < nb && cq < nb, tol);
+          store(xp, vp, cp);
+          store(xq, vq, cq);
+        }
+      }
+      __syncthreads();
+    }
+    if (rotated && gl == 0) *flag = 1;
+    __syncthreads();
+    sweeps = sweep + 1;
     if (*flag == 0) break;
   }
   __syncthreads();
@@ -520,6 +629,7 @@ __global__ void __launch_bounds__(WG)
   __shared__ int flag;
   __shared__ int rank_s;
   __shared__ double lds[LDS ? LDS_SVD : 1];
+  __shared__ double tau_s[LDS ? LDS_TAU : 1];
   IW w = iw_of(iwork, x.D);
   const int D = x.D;
   const int nm = x.n[k] * x.m[k];
@@ -530,7 +640,7 @@ __global__ void __launch_bounds__(WG)
   if (r0 > x.cap[k] || w.fr[k + 1] > x.cap[k + 1]) return;  // ranks beyond the slots
   const double delta0 = (D > 1) ? eps * scal[0] / sqrt((double)(D - 1)) : 0.0;
   double *core0 = x.data + x.off[k];
-  if (LDS && !tall && (int64_t)mb * nb + 2 * (int64_t)nb * nb <= LDS_SVD) {
+  if (LDS && !tall && (int64_t)mb * nb + 2 * (int64_t)nb * nb <= LDS_SVD && nb <= LDS_TAU) {
     // Wide unfolding M (r0 x nc): QR of B = M^T = Q R, one-sided Jacobi on
     // X = R^T (r0 x r0) with X V = W, so M = W (Q V)^T.  The kept core rows
     // (Q V)^T are orthonormal for any Jacobi tolerance (V is a product of
@@ -539,34 +649,55 @@ __global__ void __launch_bounds__(WG)
     double *Bq = lds;                        // nc x r0, then R and reflectors
     double *X = lds + (int64_t)mb * nb;      // r0 x r0
     double *Vv = X + (int64_t)nb * nb;       // r0 x r0
-    __shared__ double red[NWAVE];
     for (int64_t e = threadIdx.x; e < (int64_t)mb * nb; e += WG) {
       const int i = (int)(e % mb), j = (int)(e / mb);
       Bq[e] = carry[j + (int64_t)r0 * i];
     }
     __syncthreads();
-    double *tau = vbuf;
-    householder_qr(Bq, mb, nb, tau, red);
+    double *tau = tau_s;
+    householder_qr<NWAVE>(Bq, mb, nb, tau);
     for (int64_t e = threadIdx.x; e < (int64_t)nb * nb; e += WG) {
       const int i = (int)(e % nb), j = (int)(e / nb);
       X[e] = (j <= i) ? Bq[j + (int64_t)mb * i] : 0.0;  // X[i, j] = R[j, i]
     }
     __syncthreads();
-    jacobi<true>(X, nb, nb, Vv, nullptr, &flag, jacobi_tol(eps, nb));
+    if (nb <= 80)
+      jacobi_blk<5>(X, nb, nb, Vv, &flag, jacobi_tol(eps, nb));
+    else
+      jacobi_blk<8>(X, nb, nb, Vv, &flag, jacobi_tol(eps, nb));
     const int rank = truncate_rank(X, nb, nb, sig, w.perm, delta0, rmax, scal, &rank_s);
     if (threadIdx.x == 0) w.fr[k] = rank;
-    // F = kept columns of W (r0 x rank); Y = Q [V_kept; 0] (nc x rank)
-    double *Y = work;
+    // F = kept columns of W (r0 x rank); Y = Q [V_kept; 0] (nc x rank), in
+    // LDS over X and V (staged through registers) when it fits there
     for (int64_t e = threadIdx.x; e < (int64_t)r0 * rank; e += WG) {
       const int a = (int)(e % r0), l = (int)(e / r0);
       F[e] = X[a + (int64_t)nb * w.perm[l]];
     }
-    for (int64_t e = threadIdx.x; e < (int64_t)mb * rank; e += WG) {
-      const int i = (int)(e % mb), l = (int)(e / mb);
-      Y[e] = (i < nb) ? Vv[i + (int64_t)nb * w.perm[l]] : 0.0;
+    const int64_t ny = (int64_t)mb * rank;
+    const bool y_lds = ny <= 2 * (int64_t)nb * nb && ny <= (int64_t)YREG * WG;
+    double *Y = y_lds ? X : work;
+    if (y_lds) {
+      double yv[YREG];
+#pragma unroll
+      for (int q = 0; q < YREG; ++q) {
+        const int64_t e = threadIdx.x + (int64_t)WG * q;
+        const int i = (int)(e % mb), l = (int)(e / mb);
+        yv[q] = (e < ny && i < nb) ? Vv[i + (int64_t)nb * w.perm[l]] : 0.0;
+      }
+      __syncthreads();  // X and V are read: Y may take their place
+#pragma unroll
+      for (int q = 0; q < YREG; ++q) {
+        const int64_t e = threadIdx.x + (int64_t)WG * q;
+        if (e < ny) Y[e] = yv[q];
+      }
+    } else {
+      for (int64_t e = threadIdx.x; e < ny; e += WG) {
+        const int i = (int)(e % mb), l = (int)(e / mb);
+        Y[e] = (i < nb) ? Vv[i + (int64_t)nb * w.perm[l]] : 0.0;
+      }
     }
     __syncthreads();
-    apply_q(Bq, mb, nb, tau, Y, rank);
+    apply_q<NWAVE>(Bq, mb, nb, tau, Y, mb, rank);
     for (int64_t e = threadIdx.x; e < (int64_t)rank * nc; e += WG) {
       const int l = (int)(e % rank), col = (int)(e / rank);
       core0[e] = Y[col + (int64_t)mb * l];
@@ -588,8 +719,14 @@ __global__ void __launch_bounds__(WG)
   __syncthreads();
   // tall: the kept core is V^T, orthogonal for any stopping tolerance; wide:
   // it is built from the columns of B V, which must be orthogonal to FP64
-  const int sweeps = jacobi<false>(B, mb, nb, V, replay ? rot_log : nullptr, &flag,
-                            jacobi_tol(tall ? eps : 0.0, mb));
+  const double jtol = jacobi_tol(tall ? eps : 0.0, mb);
+  int sweeps;
+  if (both && mb <= 80 && nb <= 80)
+    sweeps = jacobi_blk<5>(B, mb, nb, V, &flag, jtol);
+  else if (both && mb <= 128 && nb <= 128)
+    sweeps = jacobi_blk<8>(B, mb, nb, V, &flag, jtol);
+  else
+    sweeps = jacobi(B, mb, nb, V, replay ? rot_log : nullptr, &flag, jtol);
   const double delta = (D > 1) ? eps * scal[0] / sqrt((double)(D - 1)) : 0.0;
   const int rank = truncate_rank(B, mb, nb, sig, w.perm, delta, rmax, scal, &rank_s);
   if (threadIdx.x == 0) w.fr[k] = rank;

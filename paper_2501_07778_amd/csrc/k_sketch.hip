@@ -21,6 +21,7 @@
 #include <cstdlib>
 
 #include "dev_gemm.h"
+#include "dev_qr.h"
 #include "dev_reduce.h"
 #include "internal.h"
 
@@ -173,70 +174,23 @@ __global__ void k_splitk_reduce(const int64_t *dims, const double *P, double *C)
   }
 }
 
-// sums over a wavefront (every lane active): DPP row moves, dev_reduce.h
-__device__ __forceinline__ double wave_sum(double v) { return dev::wave64_sum(v); }
-
-__device__ double block_sum(double v, double *red) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[w] = v;
-  __syncthreads();
-  double t = 0.0;
-#pragma unroll
-  for (int i = 0; i < NWAVE; ++i) t += red[i];
-  return t;
-}
-
-// Householder QR of the (rows x cols) sketch S; Q (rows x rq) is written to
-// `Qout` (ld = rows).  The LDS variant needs rows*cols + rows*rq <= LDS_DBL;
-// the other one works in `gw` (2 rows cols doubles of global memory).
+// Householder QR of the (rows x cols) sketch S; Q (rows x rq) is formed in
+// place of the reflectors and written to `Qout` (ld = rows).  The LDS
+// variant needs rows*cols <= LDS_DBL; the other one works in `gw` (rows
+// cols doubles of global memory, then the reflector factors).
 template <bool LDS>
 __global__ void __launch_bounds__(WG) k_sketch_qr(const double *S, int rows, int cols,
                                                   double *Qout, double *gw) {
   __shared__ double lds[LDS ? LDS_DBL : 1];
   __shared__ double tau_l[LDS_TAU];
-  __shared__ double red[NWAVE];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kmax = rows < cols ? rows : cols;
   double *W = LDS ? lds : gw;
   double *tau = LDS ? tau_l : gw + 2 * rows * cols;
-  // Q in LDS after W when both fit, otherwise in global scratch
-  const bool q_lds = LDS && rows * cols + rows * kmax <= LDS_DBL;
   for (int e = threadIdx.x; e < rows * cols; e += WG) W[e] = S[e];
   __syncthreads();
-  for (int j = 0; j < kmax; ++j) {
-    double *wj = W + rows * j;
-    double p = 0.0;
-    for (int i = j + 1 + threadIdx.x; i < rows; i += WG) p += wj[i] * wj[i];
-    const double xnorm2 = block_sum(p, red);
-    const double alpha = wj[j];
-    double t = 0.0, beta = alpha, scale = 0.0;
-    if (xnorm2 > 0.0) {
-      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-      t = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    __syncthreads();
-    if (t != 0.0)
-      for (int i = j + 1 + threadIdx.x; i < rows; i += WG) wj[i] *= scale;
-    if (threadIdx.x == 0) {
-      wj[j] = beta;
-      tau[j] = t;
-    }
-    __syncthreads();
-    if (t != 0.0) dev::reflect_cols<NWAVE>(wj, j, rows, t, W, rows, j + 1, cols);
-    __syncthreads();
-  }
-  double *Q = q_lds ? W + rows * cols : gw + rows * cols;
-  for (int e = threadIdx.x; e < rows * kmax; e += WG) Q[e] = ((e % rows) == (e / rows)) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int j = kmax - 1; j >= 0; --j) {
-    const double t = tau[j];
-    if (t != 0.0) dev::reflect_cols<NWAVE>(W + rows * j, j, rows, t, Q, rows, j, kmax);
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < rows * kmax; e += WG) Qout[e] = Q[e];
+  dev::householder_qr<NWAVE>(W, rows, cols, tau);
+  dev::form_q_inplace<NWAVE>(W, rows, kmax, tau);
+  for (int e = threadIdx.x; e < rows * kmax; e += WG) Qout[e] = W[e];
 }
 
 __global__ void k_copy(const double *src, double *dst, const int *r1, int mul, int r1cap) {
