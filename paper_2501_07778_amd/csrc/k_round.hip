@@ -184,21 +184,22 @@ __device__ __forceinline__ double group_sum(double v) {
 }
 
 // Reciprocal and reciprocal square root from the hardware estimates
-// (v_rcp_f64, v_rsq_f64) and two Newton steps each, which take them to
-// about one ulp; for the positive normal arguments of the rotations below.
+// (v_rcp_f64, v_rsq_f64, about 23 correct bits) refined by Newton steps:
+// one step gives about 46 bits, two about one ulp.  For the positive normal
+// arguments of the rotations below.
+template <int STEPS>
 __device__ __forceinline__ double rcp_nr(double x) {
   double y = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, y, 1.0);
-  y = fma(y, e, y);
-  e = fma(-x, y, 1.0);
-  return fma(y, e, y);
+#pragma unroll
+  for (int i = 0; i < STEPS; ++i) y = fma(y, fma(-x, y, 1.0), y);
+  return y;
 }
+template <int STEPS>
 __device__ __forceinline__ double rsq_nr(double x) {
   double y = __builtin_amdgcn_rsq(x);
-  double e = fma(-x * y, y, 1.0);
-  y = fma(0.5 * y, e, y);
-  e = fma(-x * y, y, 1.0);
-  return fma(0.5 * y, e, y);
+#pragma unroll
+  for (int i = 0; i < STEPS; ++i) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
 }
 
 // The Jacobi rotation of a column pair with squared norms al, be and inner
@@ -207,8 +208,9 @@ __device__ __forceinline__ double rsq_nr(double x) {
 // then zeta = (be - al) / (2 ga), t = sign(zeta) / (|zeta| + sqrt(1 +
 // zeta^2)) (the smaller root of t^2 + 2 zeta t - 1 = 0), c = 1 / sqrt(1 +
 // t^2), s = c t.  Only c must be accurate (c^2 + s^2 = 1 to rounding
-// whatever t is), so the chain uses the refined estimates above; |zeta|
-// beyond 5e149 gives t = 1 / (2 zeta) and a ga below 1e-290 the IEEE chain.
+// whatever t is): it takes two Newton steps, zeta and t one (t to about 46
+// bits, which only steers the rotation); |zeta| beyond 5e149 gives t = 1 /
+// (2 zeta) and a ga below 1e-290 the IEEE chain.
 __device__ __forceinline__ bool jac_angle(double al, double be, double ga, double tol, double &c,
                                           double &sn, double &t) {
   if (!(ga != 0.0 &&
@@ -218,14 +220,14 @@ __device__ __forceinline__ bool jac_angle(double al, double be, double ga, doubl
   if (fabs(d) > 1e150 * fabs(ga)) {
     t = ga / d;
   } else if (fabs(ga) >= 1e-290) {
-    const double zeta = 0.5 * d * rcp_nr(ga);
+    const double zeta = 0.5 * d * rcp_nr<1>(ga);
     const double h = fma(zeta, zeta, 1.0);
-    t = copysign(rcp_nr(fabs(zeta) + h * rsq_nr(h)), zeta >= 0.0 ? 1.0 : -1.0);
+    t = copysign(rcp_nr<1>(fabs(zeta) + h * rsq_nr<1>(h)), zeta >= 0.0 ? 1.0 : -1.0);
   } else {
     const double zeta = d / (2.0 * ga);
     t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   }
-  c = rsq_nr(fma(t, t, 1.0));
+  c = rsq_nr<2>(fma(t, t, 1.0));
   sn = c * t;
   return true;
 }
@@ -354,29 +356,35 @@ template <int K>
 __device__ __forceinline__ bool jac_pair(double (&xp)[K], double (&xq)[K], double (&vp)[K],
                                          double (&vq)[K], double &al, double &be, bool act,
                                          double tol) {
-  double ga = 0.0;
+  double g0 = 0.0, g1 = 0.0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) ga = fma(xp[k], xq[k], ga);
-  ga = group_sum(ga);
+  for (int k = 0; k < K; k += 2) g0 = fma(xp[k], xq[k], g0);
+#pragma unroll
+  for (int k = 1; k < K; k += 2) g1 = fma(xp[k], xq[k], g1);
+  const double ga = group_sum(g0 + g1);
   double c, sn, t;
   if (!(act && jac_angle(al, be, ga, tol, c, sn, t))) return false;
-  double np = 0.0, nq = 0.0;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const double u = xp[k], v = xq[k];
-    xp[k] = c * u - sn * v;
-    xq[k] = sn * u + c * v;
-    np = fma(xp[k], xp[k], np);
-    nq = fma(xq[k], xq[k], nq);
+    xq[k] = fma(sn, u, c * v);
+    xp[k] = fma(c, u, -(sn * v));
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const double u = vp[k], v = vq[k];
-    vp[k] = c * u - sn * v;
-    vq[k] = sn * u + c * v;
+    vq[k] = fma(sn, u, c * v);
+    vp[k] = fma(c, u, -(sn * v));
   }
   double ap = al - t * ga, aq = be + t * ga;
   if (!(ap >= 0.25 * al) || !(aq >= 0.25 * be)) {
+    // cancellation: measure instead (uniform over the group)
+    double np = 0.0, nq = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      np = fma(xp[k], xp[k], np);
+      nq = fma(xq[k], xq[k], nq);
+    }
     ap = group_sum(np);
     aq = group_sum(nq);
   }
@@ -416,13 +424,18 @@ __device__ int jacobi_blk(double *B, int mb, int nb, double *V, int *flag, doubl
   for (int64_t e = threadIdx.x; e < (int64_t)nb * nb; e += WG)
     V[e] = ((e % nb) == (e / nb)) ? 1.0 : 0.0;
   const int nblk = (nb + 3) / 4, NB = nblk + (nblk & 1);
+  // loads read an in-bounds element for every lane (the last row or column
+  // instead of one past the end) and zero what lies outside
   auto load = [&](double (&x)[K], double (&v)[K], int c) {
     const bool in = c < nb;
+    const int cc = in ? c : nb - 1;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int l = gl + GL * k;
-      x[k] = (in && l < mb) ? B[l + (int64_t)mb * c] : 0.0;
-      v[k] = (in && l < nb) ? V[l + (int64_t)nb * c] : 0.0;
+      const double bx = B[(l < mb ? l : mb - 1) + (int64_t)mb * cc];
+      const double vx = V[(l < nb ? l : nb - 1) + (int64_t)nb * cc];
+      x[k] = (in && l < mb) ? bx : 0.0;
+      v[k] = (in && l < nb) ? vx : 0.0;
     }
   };
   auto store = [&](const double (&x)[K], const double (&v)[K], int c) {
@@ -664,7 +677,7 @@ __global__ void __launch_bounds__(WG)
     if (nb <= 80)
       jacobi_blk<5>(X, nb, nb, Vv, &flag, jacobi_tol(eps, nb));
     else
-      jacobi_blk<8>(X, nb, nb, Vv, &flag, jacobi_tol(eps, nb));
+      jacobi_blk<6>(X, nb, nb, Vv, &flag, jacobi_tol(eps, nb));
     const int rank = truncate_rank(X, nb, nb, sig, w.perm, delta0, rmax, scal, &rank_s);
     if (threadIdx.x == 0) w.fr[k] = rank;
     // F = kept columns of W (r0 x rank); Y = Q [V_kept; 0] (nc x rank), in
@@ -723,8 +736,8 @@ __global__ void __launch_bounds__(WG)
   int sweeps;
   if (both && mb <= 80 && nb <= 80)
     sweeps = jacobi_blk<5>(B, mb, nb, V, &flag, jtol);
-  else if (both && mb <= 128 && nb <= 128)
-    sweeps = jacobi_blk<8>(B, mb, nb, V, &flag, jtol);
+  else if (both && mb <= 96 && nb <= 96)
+    sweeps = jacobi_blk<6>(B, mb, nb, V, &flag, jtol);
   else
     sweeps = jacobi(B, mb, nb, V, replay ? rot_log : nullptr, &flag, jtol);
   const double delta = (D > 1) ? eps * scal[0] / sqrt((double)(D - 1)) : 0.0;

@@ -100,8 +100,8 @@ __global__ void k_sketch_T(TTView y, TTView om, int k, const double *Wn, double 
   }
 }
 
-using dev::GT;
-using dev::gemm_tile;
+using TN80 = dev::TileN80;  // 64 x 80 tiles: outputs with an l-wide column range
+using TM80 = dev::TileM80;  // 80 x 64 tiles: outputs with an l-wide row range
 
 constexpr int KC = 256;  // K range per block of the split-K products
 
@@ -125,9 +125,9 @@ __global__ void __launch_bounds__(256) k_sketch_W(TTView y, TTView om, int k, co
   const bool bad = beyond_caps(y, k);
   const int M = bad ? 0 : y.rk[k], K = y.n[k] * y.m[k] * y.rk[k + 1], N = om.cap[k];
   publish_dims(dims, M, N, K);
-  if (bad || blockIdx.x * GT >= M || blockIdx.y * GT >= N) return;
-  dev::gemm_tile_k<false>(y.data + y.off[k], M, Tk, K, Pw, M, N, K, blockIdx.x, blockIdx.y,
-                          blockIdx.z, KC);
+  if (bad || blockIdx.x * TN80::TM >= M || blockIdx.y * TN80::TN >= N) return;
+  dev::gemm_tile_k_w<false, TN80>(y.data + y.off[k], M, Tk, K, Pw, M, N, K, blockIdx.x,
+                                  blockIdx.y, blockIdx.z, KC);
 }
 
 // S ((lz nm) x l_{k+1}) = Z (lz nm x a_{k+1}) W_{k+1}, split over K
@@ -137,8 +137,9 @@ __global__ void __launch_bounds__(256) k_sketch_S(TTView y, TTView om, int k, in
   const bool bad = beyond_caps(y, k);
   const int M = bad ? 0 : lz * y.n[k] * y.m[k], K = y.rk[k + 1], N = om.cap[k + 1];
   publish_dims(dims, M, N, K);
-  if (bad || blockIdx.x * GT >= M || blockIdx.y * GT >= N) return;
-  dev::gemm_tile_k<false>(Z, M, Wn, K, Ps, M, N, K, blockIdx.x, blockIdx.y, blockIdx.z, KC);
+  if (bad || blockIdx.x * TN80::TM >= M || blockIdx.y * TN80::TN >= N) return;
+  dev::gemm_tile_k_w<false, TN80>(Z, M, Wn, K, Ps, M, N, K, blockIdx.x, blockIdx.y, blockIdx.z,
+                                  KC);
 }
 
 // Mq (rq x a_{k+1}) = Q^T (rq x lz nm) Z (lz nm x a_{k+1})
@@ -146,8 +147,9 @@ __global__ void __launch_bounds__(256) k_sketch_M(TTView y, int k, int lz, int r
                                                   const double *Q, const double *Z, double *Mq) {
   if (beyond_caps(y, k)) return;
   const int M = rq, K = lz * y.n[k] * y.m[k], N = y.rk[k + 1];
-  if (blockIdx.x * GT >= M || blockIdx.y * GT >= N) return;
-  gemm_tile<true>(Q, K, Z, K, Mq, M, M, N, K, blockIdx.x, blockIdx.y);
+  if (blockIdx.x * TM80::TM >= M || blockIdx.y * TM80::TN >= N) return;
+  dev::gemm_tile_mfma_w<true, TM80::WM, TM80::WN, TM80::BM, TM80::BN>(Q, K, Z, K, Mq, M, M, N, K,
+                                                                      blockIdx.x, blockIdx.y);
 }
 
 // Z' (rq x nm_{k+1} a_{k+2}) = Mq (rq x a_{k+1}) Y_{k+1}, split over K
@@ -156,9 +158,9 @@ __global__ void __launch_bounds__(256) k_sketch_Z(TTView y, int k, int rq, const
   const bool bad = beyond_caps(y, k);
   const int M = bad ? 0 : rq, K = y.rk[k + 1], N = y.n[k + 1] * y.m[k + 1] * y.rk[k + 2];
   publish_dims(dims, M, N, K);
-  if (bad || blockIdx.x * GT >= M || blockIdx.y * GT >= N) return;
-  dev::gemm_tile_k<false>(Mq, M, y.data + y.off[k + 1], K, Pz, M, N, K, blockIdx.x, blockIdx.y,
-                          blockIdx.z, KC);
+  if (bad || blockIdx.x * TM80::TM >= M || blockIdx.y * TM80::TN >= N) return;
+  dev::gemm_tile_k_w<false, TM80>(Mq, M, y.data + y.off[k + 1], K, Pz, M, N, K, blockIdx.x,
+                                  blockIdx.y, blockIdx.z, KC);
 }
 
 // C = sum of the partials of the product launched just before (sizes from
@@ -336,7 +338,7 @@ hipError_t sketch_tt(const TTView &y, int ell, uint64_t seed, uint64_t call, dou
     int blocks = (int)std::min<int64_t>((tn + 255) / 256, 4096);
     hipLaunchKernelGGL(k_sketch_T, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, y, L.om, k,
                        L.W[k + 1], L.T);
-    const int mt = (y.cap[k] + GT - 1) / GT, nt = (d.l[k] + GT - 1) / GT;
+    const int mt = (y.cap[k] + TN80::TM - 1) / TN80::TM, nt = (d.l[k] + TN80::TN - 1) / TN80::TN;
     const int ns = split_of(y.n[k] * y.m[k] * y.cap[k + 1]);
     hipLaunchKernelGGL(k_sketch_W, dim3(mt, nt, ns), dim3(256), 0, s, y, L.om, k, L.T, L.P,
                        L.dims);
@@ -355,7 +357,7 @@ hipError_t sketch_tt(const TTView &y, int ell, uint64_t seed, uint64_t call, dou
     const int lz = d.lz[k], rq = d.lz[k + 1];
     const int rows = lz * y.n[k] * y.m[k], cols = d.l[k + 1];
     {
-      const int mt = (rows + GT - 1) / GT, nt = (cols + GT - 1) / GT;
+      const int mt = (rows + TN80::TM - 1) / TN80::TM, nt = (cols + TN80::TN - 1) / TN80::TN;
       const int ns = split_of(y.cap[k + 1]);
       hipLaunchKernelGGL(k_sketch_S, dim3(mt, nt, ns), dim3(256), 0, s, y, L.om, k, lz, L.Z[cur],
                          L.W[k + 1], L.P, L.dims);
@@ -370,13 +372,13 @@ hipError_t sketch_tt(const TTView &y, int ell, uint64_t seed, uint64_t call, dou
       hipLaunchKernelGGL(k_sketch_qr<false>, dim3(1), dim3(WG), 0, s, L.S, rows, cols, Q, L.Qw);
     ktimer_end(th, s);
     {
-      const int mt = (rq + GT - 1) / GT, nt = (y.cap[k + 1] + GT - 1) / GT;
+      const int mt = (rq + TM80::TM - 1) / TM80::TM, nt = (y.cap[k + 1] + TM80::TN - 1) / TM80::TN;
       hipLaunchKernelGGL(k_sketch_M, dim3(mt, nt), dim3(256), 0, s, y, k, lz, rq, Q, L.Z[cur],
                          L.Mq);
     }
     {
-      const int mt = (rq + GT - 1) / GT;
-      const int nt = (y.n[k + 1] * y.m[k + 1] * y.cap[k + 2] + GT - 1) / GT;
+      const int mt = (rq + TM80::TM - 1) / TM80::TM;
+      const int nt = (y.n[k + 1] * y.m[k + 1] * y.cap[k + 2] + TM80::TN - 1) / TM80::TN;
       const int ns = split_of(y.cap[k + 1]);
       hipLaunchKernelGGL(k_sketch_Z, dim3(mt, nt, ns), dim3(256), 0, s, y, k, rq, L.Mq, L.P,
                          L.dims);
