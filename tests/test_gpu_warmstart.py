@@ -383,8 +383,11 @@ def test_learned_start_end_to_end_level6(P):
     hist = net.fit(acols, tcols.t(), 64, 60, 3e-3, 1e-4, 11, nrow, ranks)
     print("core loss: first pass %.3e, last %.3e" % (hist[0], hist[-1]), flush=True)
     assert hist[-1] < 0.05 * hist[0], (hist[0], hist[-1])
-    held = np.stack([W.warmstart_params(s) for s in range(4096, 4096 + 4)], axis=1)
-    sopts = P.SolveOpts(tol=1e-6, eps=0.0, rmax=16, rmax_in=4, maxit_out=80, method="als",
+    # sweep counts of single solves vary widely with the start (cold 30 to
+    # more than 80 here), so the average is taken over 8 held-out loads and
+    # the sweep limit leaves every solve room to converge
+    held = np.stack([W.warmstart_params(s) for s in range(4096, 4096 + 8)], axis=1)
+    sopts = P.SolveOpts(tol=1e-6, eps=0.0, rmax=16, rmax_in=4, maxit_out=200, method="als",
                         seed=1)
     rows = LS.compare_starts(net, W.cantilever_two_component, level, held, nrow, ranks, sopts)
     for j, r in enumerate(rows):
