@@ -419,7 +419,8 @@ __device__ __forceinline__ void jac_swap(double (&x)[K], double (&v)[K], double 
 // sweep (three rounds, two pairs per block).  Every column pair is visited
 // once per sweep, as in the cyclic order.
 template <int K>
-__device__ int jacobi_blk(double *B, int mb, int nb, double *V, int *flag, double tol) {
+__device__ __forceinline__ int jacobi_blk(double *B, int mb, int nb, double *V, int *flag,
+                                           double tol) {
   const int gl = threadIdx.x & 15, g = (threadIdx.x >> 4) & 3, wave = threadIdx.x >> 6;
   for (int64_t e = threadIdx.x; e < (int64_t)nb * nb; e += WG)
     V[e] = ((e % nb) == (e / nb)) ? 1.0 : 0.0;
