@@ -38,9 +38,12 @@ __device__ void householder_qr(double *W, int rows, int cols, double *tau) {
     const double alpha = wj[j];
     double t = 0.0, beta = alpha, scale = 1.0;
     if (xnorm2 > 0.0) {
-      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-      t = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
+      // square root and quotients from the refined hardware estimates
+      // (about one ulp); every wavefront forms them, on its own chain
+      const double h = fma(alpha, alpha, xnorm2);
+      beta = -copysign(h * rsq_nr<2>(h), alpha);
+      t = (beta - alpha) * rcp_nr<2>(beta);
+      scale = rcp_nr<2>(alpha - beta);
     }
     if (t != 0.0) reflect_cols<NW>(wj, j, rows, scale, t, W, rows, j + 1, cols);
     if (wave == 0 && j > 0) finish(j - 1);
@@ -72,20 +75,30 @@ __device__ void form_q(const double *W, int rows, int kq, const double *tau, dou
 // Q (rows x kq) = H_0 ... H_{kq-1} [I; 0] formed in place of the first kq
 // columns of W (LAPACK's order of dorg2r): for j = kq-1 down to 0, H_j is
 // applied to the columns j+1.. (already the trailing columns of Q, zero
-// above row j+1) and column j becomes H_j e_j = e_j - tau_j v_j.  Whatever W
-// held on and above the diagonal (R) is overwritten.
+// above row j+1) and column j becomes H_j e_j = e_j - tau_j v_j.  Column
+// j+1 is formed at step j by wavefront 0, which owns it in reflect_cols,
+// just before it applies H_j to it, so a step needs one barrier.  Whatever
+// W held on and above the diagonal (R) is overwritten.
 template <int NW>
 __device__ void form_q_inplace(double *W, int rows, int kq, const double *tau) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // wavefront 0: column c <- H_c e_c from its reflector
+  auto form = [&](int c) {
+    double *wc = W + (int64_t)rows * c;
+    const double t = tau[c];
+    for (int i = lane; i < rows; i += 64)
+      wc[i] = (i < c) ? 0.0 : ((i == c) ? 1.0 - t : -t * wc[i]);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  };
   __syncthreads();
   for (int j = kq - 1; j >= 0; --j) {
     const double t = tau[j];
-    double *wj = W + (int64_t)rows * j;
-    if (t != 0.0) reflect_cols<NW>(wj, j, rows, 1.0, t, W, rows, j + 1, kq);
-    __syncthreads();
-    for (int i = threadIdx.x; i < rows; i += NW * 64)
-      wj[i] = (i < j) ? 0.0 : ((i == j) ? 1.0 - t : -t * wj[i]);
+    if (wave == 0 && j + 1 < kq) form(j + 1);
+    if (t != 0.0) reflect_cols<NW>(W + (int64_t)rows * j, j, rows, 1.0, t, W, rows, j + 1, kq);
     __syncthreads();
   }
+  if (wave == 0 && kq > 0) form(0);
+  __syncthreads();
 }
 
 // Y (rows x ncols, ld ldy) <- H_0 H_1 ... H_{kq-1} Y

@@ -183,24 +183,8 @@ __device__ __forceinline__ double group_sum(double v) {
   return dev::row16_sum(v);
 }
 
-// Reciprocal and reciprocal square root from the hardware estimates
-// (v_rcp_f64, v_rsq_f64, about 23 correct bits) refined by Newton steps:
-// one step gives about 46 bits, two about one ulp.  For the positive normal
-// arguments of the rotations below.
-template <int STEPS>
-__device__ __forceinline__ double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-#pragma unroll
-  for (int i = 0; i < STEPS; ++i) y = fma(y, fma(-x, y, 1.0), y);
-  return y;
-}
-template <int STEPS>
-__device__ __forceinline__ double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-#pragma unroll
-  for (int i = 0; i < STEPS; ++i) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
-  return y;
-}
+using dev::rcp_nr;
+using dev::rsq_nr;
 
 // The Jacobi rotation of a column pair with squared norms al, be and inner
 // product ga: rotate when |ga| > tol sqrt(al be) (tested with the hardware
