@@ -67,70 +67,57 @@ __device__ __forceinline__ double rsq_nr(double x) {
 namespace qtt {
 namespace dev {
 
-constexpr int REFL_REG = 4;   // reflector elements per lane held in registers
-constexpr int REFL_U = 2;     // columns per wavefront in flight at once
+constexpr int REFL_RG = 9;    // reflector rows per lane held in registers (16-lane groups)
 
 // Apply the Householder reflector H = I - t v v^T, v = [1 at row j; vs * wj
 // below it] (wj is the reflector's column, rows long, and vs a factor the
 // caller has not yet applied to it), to the columns c0 <= c < c1 of Y
-// (leading dimension ldy), one wavefront per column, NW wavefronts.  When
-// the reflector has at most 64 REFL_REG entries below row j each lane keeps
-// its part in registers and a wavefront works on REFL_U columns at once
-// (their loads, dot products and sums overlap), so a column costs a share
-// of one memory wait and one reduction latency.
+// (leading dimension ldy), NW wavefronts.  Each 16-lane group (one DPP row)
+// takes one column at a time, so a wavefront works on four columns at once
+// and a column's sum takes four DPP steps instead of a 64-lane reduction
+// (about a quarter of the instructions per column).  When the reflector
+// spans at most 16 REFL_RG rows every lane keeps its part of it (rows j +
+// lane + 16 k) in registers.
 template <int NW>
 __device__ __forceinline__ void reflect_cols(const double *wj, int j, int rows, double vs,
                                              double t, double *Y, int64_t ldy, int c0, int c1) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (rows - (j + 1) <= 64 * REFL_REG) {
+  const int gl = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  constexpr int NG = NW * 4;
+  if (rows - j <= 16 * REFL_RG) {
     // rows past the end read row j instead (in bounds) with a zero weight
-    int iv[REFL_REG];
-    bool ok[REFL_REG];
-    double wv[REFL_REG];
+    int iv[REFL_RG];
+    double wv[REFL_RG];
 #pragma unroll
-    for (int k = 0; k < REFL_REG; ++k) {
-      const int i = j + 1 + lane + 64 * k;
-      ok[k] = i < rows;
-      iv[k] = ok[k] ? i : j;
+    for (int k = 0; k < REFL_RG; ++k) {
+      const int i = j + gl + 16 * k;
+      const bool ok = i < rows;
+      iv[k] = ok ? i : j;
       const double w = wj[iv[k]];
-      wv[k] = ok[k] ? vs * w : 0.0;
+      wv[k] = (i == j) ? 1.0 : (ok ? vs * w : 0.0);
     }
-    for (int cb = c0 + wave; cb < c1; cb += NW * REFL_U) {
-      double yv[REFL_U][REFL_REG], s[REFL_U];
+    for (int c = c0 + grp; c < c1; c += NG) {
+      double *yc = Y + ldy * c;
+      double yv[REFL_RG];
 #pragma unroll
-      for (int u = 0; u < REFL_U; ++u) {
-        const int c = cb + NW * u;
-        const double *yc = Y + ldy * (c < c1 ? c : cb);
-        const double y0 = yc[j];
-        s[u] = (lane == 0) ? y0 : 0.0;
+      for (int k = 0; k < REFL_RG; ++k) yv[k] = yc[iv[k]];
+      double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-        for (int k = 0; k < REFL_REG; ++k) yv[u][k] = yc[iv[k]];
+      for (int k = 0; k < REFL_RG; k += 2) s0 = fma(wv[k], yv[k], s0);
 #pragma unroll
-        for (int k = 0; k < REFL_REG; ++k) s[u] = fma(wv[k], yv[u][k], s[u]);
-      }
+      for (int k = 1; k < REFL_RG; k += 2) s1 = fma(wv[k], yv[k], s1);
+      const double s = row16_sum(s0 + s1) * t;
 #pragma unroll
-      for (int u = 0; u < REFL_U; ++u) s[u] = wave64_sum(s[u]) * t;
-#pragma unroll
-      for (int u = 0; u < REFL_U; ++u) {
-        const int c = cb + NW * u;
-        if (c < c1) {
-          double *yc = Y + ldy * c;
-          if (lane == 0) yc[j] -= s[u];
-#pragma unroll
-          for (int k = 0; k < REFL_REG; ++k)
-            if (ok[k]) yc[iv[k]] = yv[u][k] - s[u] * wv[k];
-        }
-      }
+      for (int k = 0; k < REFL_RG; ++k)
+        if (j + gl + 16 * k < rows) yc[iv[k]] = yv[k] - s * wv[k];
     }
     return;
   }
-  for (int c = c0 + wave; c < c1; c += NW) {
+  for (int c = c0 + grp; c < c1; c += NG) {
     double *yc = Y + ldy * c;
-    double s = (lane == 0) ? yc[j] : 0.0;
-    for (int i = j + 1 + lane; i < rows; i += 64) s = fma(vs * wj[i], yc[i], s);
-    s = wave64_sum(s) * t;
-    if (lane == 0) yc[j] -= s;
-    for (int i = j + 1 + lane; i < rows; i += 64) yc[i] -= s * (vs * wj[i]);
+    double s = 0.0;
+    for (int i = j + gl; i < rows; i += 16) s = fma(i == j ? 1.0 : vs * wj[i], yc[i], s);
+    s = row16_sum(s) * t;
+    for (int i = j + gl; i < rows; i += 16) yc[i] -= s * (i == j ? 1.0 : vs * wj[i]);
   }
 }
 
