@@ -38,12 +38,9 @@ __device__ void householder_qr(double *W, int rows, int cols, double *tau) {
     const double alpha = wj[j];
     double t = 0.0, beta = alpha, scale = 1.0;
     if (xnorm2 > 0.0) {
-      // square root and quotients from the refined hardware estimates
-      // (about one ulp); every wavefront forms them, on its own chain
-      const double h = fma(alpha, alpha, xnorm2);
-      beta = -copysign(h * rsq_nr<2>(h), alpha);
-      t = (beta - alpha) * rcp_nr<2>(beta);
-      scale = rcp_nr<2>(alpha - beta);
+      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+      t = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
     }
     if (t != 0.0) reflect_cols<NW>(wj, j, rows, scale, t, W, rows, j + 1, cols);
     if (wave == 0 && j > 0) finish(j - 1);
@@ -88,7 +85,10 @@ __device__ void form_q_inplace(double *W, int rows, int kq, const double *tau) {
     const double t = tau[c];
     for (int i = lane; i < rows; i += 64)
       wc[i] = (i < c) ? 0.0 : ((i == c) ? 1.0 - t : -t * wc[i]);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    // other lanes of this wavefront read these rows next: wait for the stores
+    // (W may be in global memory, where a wavefront's accesses to one address
+    // from different lanes are not ordered without it)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   };
   __syncthreads();
   for (int j = kq - 1; j >= 0; --j) {

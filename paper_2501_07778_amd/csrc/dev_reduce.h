@@ -75,9 +75,9 @@ constexpr int REFL_RG = 9;    // reflector rows per lane held in registers (16-l
 // (leading dimension ldy), NW wavefronts.  Each 16-lane group (one DPP row)
 // takes one column at a time, so a wavefront works on four columns at once
 // and a column's sum takes four DPP steps instead of a 64-lane reduction
-// (about a quarter of the instructions per column).  When the reflector
-// spans at most 16 REFL_RG rows every lane keeps its part of it (rows j +
-// lane + 16 k) in registers.
+// (about a quarter of the instructions per column), when the reflector
+// spans at most 16 REFL_RG rows; every lane then keeps its part of it (rows
+// j + lane + 16 k) in registers.
 template <int NW>
 __device__ __forceinline__ void reflect_cols(const double *wj, int j, int rows, double vs,
                                              double t, double *Y, int64_t ldy, int c0, int c1) {
@@ -112,12 +112,18 @@ __device__ __forceinline__ void reflect_cols(const double *wj, int j, int rows, 
     }
     return;
   }
-  for (int c = c0 + grp; c < c1; c += NG) {
+  // longer reflectors: one column per wavefront and a 64-lane sum, so each
+  // lane accumulates a quarter as many terms in sequence as a 16-lane group
+  // would (the long QRs of the assembly, whose rounding error the solves at
+  // high condition numbers see)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = c0 + wave; c < c1; c += NW) {
     double *yc = Y + ldy * c;
-    double s = 0.0;
-    for (int i = j + gl; i < rows; i += 16) s = fma(i == j ? 1.0 : vs * wj[i], yc[i], s);
-    s = row16_sum(s) * t;
-    for (int i = j + gl; i < rows; i += 16) yc[i] -= s * (i == j ? 1.0 : vs * wj[i]);
+    double s = (lane == 0) ? yc[j] : 0.0;
+    for (int i = j + 1 + lane; i < rows; i += 64) s = fma(vs * wj[i], yc[i], s);
+    s = wave64_sum(s) * t;
+    if (lane == 0) yc[j] -= s;
+    for (int i = j + 1 + lane; i < rows; i += 64) yc[i] -= s * (vs * wj[i]);
   }
 }
 
