@@ -89,22 +89,32 @@ def step(P, K, x, y, ws, seed, compute="f64"):
 
 def measured_traffic(summary: str, source: str):
     """HBM bytes per launch of a kernel from its committed counter summary
-    in profiles/, or None once the kernel's source file has changed since
-    the counters were taken."""
+    in profiles/, or None once any source file the summary lists (the
+    kernel's file and the device headers it includes) has changed since the
+    counters were taken."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
-    summ = os.path.join(here, "profiles", summary)
-    src = os.path.join(here, "paper_2501_07778_amd", "csrc", source)
     try:
-        txt = open(summ).read()
-        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+        txt = open(os.path.join(here, "profiles", summary)).read()
     except OSError:
         return None
-    vals = dict(line.split(": ", 1) for line in txt.splitlines() if ": " in line and
-                (line.startswith("traffic_bytes") or line.startswith("source_sha1")))
-    if vals.get("source_sha1(paper_2501_07778_amd/csrc/%s)" % source, "").strip() != sha:
+    shas = {}
+    traffic = None
+    for line in txt.splitlines():
+        if line.startswith("source_sha1(") and "): " in line:
+            path, val = line[len("source_sha1("):].split("): ", 1)
+            shas[path] = val.strip()
+        elif line.startswith("traffic_bytes_per_launch: "):
+            traffic = int(line.split(": ", 1)[1])
+    if traffic is None or "paper_2501_07778_amd/csrc/%s" % source not in shas:
         return None
-    return int(vals["traffic_bytes_per_launch"])
+    for path, val in shas.items():
+        try:
+            if hashlib.sha1(open(os.path.join(here, path), "rb").read()).hexdigest() != val:
+                return None
+        except OSError:
+            return None
+    return traffic
 
 
 def matvec_roofline(P, torch, K, x):
