@@ -93,8 +93,21 @@ __global__ void k_sketch_T(TTView y, TTView om, int k, const double *Wn, double 
     const int row = (int)(e % ((int64_t)nm * a1));
     const int l = (int)(e / ((int64_t)nm * a1));
     const int i = row % nm, b = row / nm;
+    // operands of eight terms loaded before they are summed (same order),
+    // so eight loads are in flight instead of one
     double acc = 0.0;
-    for (int lp = 0; lp < l1; ++lp)
+    int lp = 0;
+    for (; lp + 8 <= l1; lp += 8) {
+      double wv[8], ov[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        wv[u] = Wn[b + (int64_t)a1 * (lp + u)];
+        ov[u] = o[l + (int64_t)lk * (i + (int64_t)nm * (lp + u))];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = fma(wv[u], ov[u], acc);
+    }
+    for (; lp < l1; ++lp)
       acc = fma(Wn[b + (int64_t)a1 * lp], o[l + (int64_t)lk * (i + (int64_t)nm * lp)], acc);
     Tk[e] = acc;
   }
@@ -170,8 +183,17 @@ __global__ void k_splitk_reduce(const int64_t *dims, const double *P, double *C)
   const int used = (int)dims[1];
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne;
        e += (int64_t)gridDim.x * blockDim.x) {
+    // partials loaded eight at a time, summed in order
     double acc = 0.0;
-    for (int z = 0; z < used; ++z) acc += P[(int64_t)z * ne + e];
+    int z = 0;
+    for (; z + 8 <= used; z += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = P[(int64_t)(z + u) * ne + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; z < used; ++z) acc += P[(int64_t)z * ne + e];
     C[e] = acc;
   }
 }
