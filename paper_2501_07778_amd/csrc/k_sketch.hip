@@ -116,16 +116,17 @@ __global__ void k_sketch_T(TTView y, TTView om, int k, const double *Wn, double 
 using TN80 = dev::TileN80;  // 64 x 80 tiles: outputs with an l-wide column range
 using TM80 = dev::TileM80;  // 80 x 64 tiles: outputs with an l-wide row range
 
-constexpr int KC = 256;  // K range per block of the split-K products
+constexpr int KC = 256;   // K range per block of the split-K products
+constexpr int KC_S = 64;  // the same for S, whose output is only a few tiles
 
 // Block (0,0,0) of a split-K product publishes the element count of its
 // output and the number of K ranges that hold data; the reduction that
 // follows on the stream reads them (the sizes live in device memory).
-__device__ __forceinline__ void publish_dims(int64_t *dims, int M, int N, int K) {
+__device__ __forceinline__ void publish_dims(int64_t *dims, int M, int N, int K, int kcmin) {
   if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) {
     const int nz = (int)gridDim.z;
     int kc = (K + nz - 1) / nz;
-    kc = kc > KC ? kc : KC;
+    kc = kc > kcmin ? kc : kcmin;
     const int used = K > 0 ? (K + kc - 1) / kc : 0;
     dims[0] = (int64_t)M * N;
     dims[1] = used < nz ? used : nz;
@@ -137,7 +138,7 @@ __global__ void __launch_bounds__(256) k_sketch_W(TTView y, TTView om, int k, co
                                                   double *Pw, int64_t *dims) {
   const bool bad = beyond_caps(y, k);
   const int M = bad ? 0 : y.rk[k], K = y.n[k] * y.m[k] * y.rk[k + 1], N = om.cap[k];
-  publish_dims(dims, M, N, K);
+  publish_dims(dims, M, N, K, KC);
   if (bad || blockIdx.x * TN80::TM >= M || blockIdx.y * TN80::TN >= N) return;
   dev::gemm_tile_k_w<false, TN80>(y.data + y.off[k], M, Tk, K, Pw, M, N, K, blockIdx.x,
                                   blockIdx.y, blockIdx.z, KC);
@@ -149,10 +150,10 @@ __global__ void __launch_bounds__(256) k_sketch_S(TTView y, TTView om, int k, in
                                                   int64_t *dims) {
   const bool bad = beyond_caps(y, k);
   const int M = bad ? 0 : lz * y.n[k] * y.m[k], K = y.rk[k + 1], N = om.cap[k + 1];
-  publish_dims(dims, M, N, K);
+  publish_dims(dims, M, N, K, KC_S);
   if (bad || blockIdx.x * TN80::TM >= M || blockIdx.y * TN80::TN >= N) return;
   dev::gemm_tile_k_w<false, TN80>(Z, M, Wn, K, Ps, M, N, K, blockIdx.x, blockIdx.y, blockIdx.z,
-                                  KC);
+                                  KC_S);
 }
 
 // Mq (rq x a_{k+1}) = Q^T (rq x lz nm) Z (lz nm x a_{k+1})
@@ -170,7 +171,7 @@ __global__ void __launch_bounds__(256) k_sketch_Z(TTView y, int k, int rq, const
                                                   double *Pz, int64_t *dims) {
   const bool bad = beyond_caps(y, k);
   const int M = bad ? 0 : rq, K = y.rk[k + 1], N = y.n[k + 1] * y.m[k + 1] * y.rk[k + 2];
-  publish_dims(dims, M, N, K);
+  publish_dims(dims, M, N, K, KC);
   if (bad || blockIdx.x * TM80::TM >= M || blockIdx.y * TM80::TN >= N) return;
   dev::gemm_tile_k_w<false, TM80>(Mq, M, y.data + y.off[k + 1], K, Pz, M, N, K, blockIdx.x,
                                   blockIdx.y, blockIdx.z, KC);
@@ -263,8 +264,8 @@ SketchDims sketch_dims(const TTView &y, int ell) {
 }
 
 // split count for a product with K of at most kcap
-int split_of(int64_t kcap) {
-  const int64_t s = (kcap + KC - 1) / KC;
+int split_of(int64_t kcap, int kc = KC) {
+  const int64_t s = (kcap + kc - 1) / kc;
   return (int)std::max<int64_t>(1, std::min<int64_t>(s, 32));
 }
 
@@ -320,7 +321,7 @@ SketchLayout sketch_layout(const TTView &y, const SketchDims &d, double *ws) {
   for (int k = 0; k < D; ++k) {
     pmax = std::max<int64_t>(pmax, (int64_t)split_of(y.n[k] * y.m[k] * y.cap[k + 1]) *
                                        y.cap[k] * d.l[k]);
-    pmax = std::max<int64_t>(pmax, (int64_t)split_of(y.cap[k + 1]) * d.lz[k] * y.n[k] * y.m[k] *
+    pmax = std::max<int64_t>(pmax, (int64_t)split_of(y.cap[k + 1], KC_S) * d.lz[k] * y.n[k] * y.m[k] *
                                        d.l[k + 1]);
     if (k + 1 < D)
       pmax = std::max<int64_t>(pmax, (int64_t)split_of(y.cap[k + 1]) * d.lz[k + 1] *
@@ -380,7 +381,7 @@ hipError_t sketch_tt(const TTView &y, int ell, uint64_t seed, uint64_t call, dou
     const int rows = lz * y.n[k] * y.m[k], cols = d.l[k + 1];
     {
       const int mt = (rows + TN80::TM - 1) / TN80::TM, nt = (cols + TN80::TN - 1) / TN80::TN;
-      const int ns = split_of(y.cap[k + 1]);
+      const int ns = split_of(y.cap[k + 1], KC_S);
       hipLaunchKernelGGL(k_sketch_S, dim3(mt, nt, ns), dim3(256), 0, s, y, L.om, k, lz, L.Z[cur],
                          L.W[k + 1], L.P, L.dims);
       hipLaunchKernelGGL(k_splitk_reduce, dim3(red_blocks((int64_t)rows * cols)), dim3(256), 0, s,
