@@ -100,6 +100,33 @@ def test_round_matches_oracle(P, modes, r, eps, rmax):
         np.testing.assert_allclose(M @ M.T, np.eye(c.shape[0]), atol=1e-12)
 
 
+@pytest.mark.parametrize("modes,r", [([2] * 10, 12), ([2] * 8, 37), ([2, 3, 2, 2, 2, 2], 9)])
+def test_round_degenerate_unfoldings(P, modes, r):
+    """Degenerate inputs of the SVD steps, against the oracle's rounding:
+    x + x (core concatenation) doubles every rank with exactly dependent
+    columns, and zeroing one rank component of a middle core leaves zero
+    columns in its unfoldings.  The rounded tensors match the oracle's, the
+    ranks come back to the oracle's, and the kept cores stay orthonormal."""
+    x = _vec(31, modes, r)
+    z = [c.copy() for c in x]
+    mid = len(z) // 2
+    z[mid][:, :, 0] = 0.0
+    for y in (T.add(x, x), z):
+        ref, info = T.tt_round(y, 1e-12, return_info=True)
+        t = P.tt_from_cores(y)
+        nrm, err = P.round_(t, 1e-12, 0)
+        got = P.tt_to_cores(t)
+        yd = T.full_vector(y)
+        gd = T.full_vector(got)
+        assert nrm == pytest.approx(info["norm"], rel=1e-12)
+        assert np.linalg.norm(gd - yd) <= 1e-11 * np.linalg.norm(yd)
+        assert np.linalg.norm(gd - T.full_vector(ref)) <= 1e-11 * np.linalg.norm(yd)
+        assert t.ranks == T.ranks(ref), (t.ranks, T.ranks(ref))
+        for c in got[1:]:
+            M = c.reshape(c.shape[0], -1, order="F")
+            np.testing.assert_allclose(M @ M.T, np.eye(c.shape[0]), atol=1e-12)
+
+
 def test_round_of_matvec_product(P):
     """The hot-path combination: round(K x) against the oracle."""
     from oracle import assembly as A
