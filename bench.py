@@ -193,10 +193,15 @@ def rel_diff(P, a, b) -> float:
     return (max(aa + bb - 2.0 * ab, 0.0) ** 0.5) / bb ** 0.5
 
 
+MIXED_TOL = 1e-6   # relative error the metric allows against the FP64 GPU step
+
+
 def mixed_precision(P, torch, K, x, ws, steps):
     """The same step with the product in FP32 and BF16 (FP32 accumulation;
-    sketch GEMMs, QR and SVD stay FP64), same sketch seed: time per step and
-    relative error of the result against the FP64 step."""
+    sketch GEMMs, QR and SVD stay FP64), same sketch seed: time per step,
+    relative error of the result against the FP64 step, and whether that
+    error is within the metric's 1e-6 (BF16 products are not: about 1e-2,
+    and nothing refines them)."""
     y64 = step(P, K, x, None, ws, 0, "f64")
     out = {}
     for comp in ("f32", "bf16"):
@@ -207,8 +212,9 @@ def mixed_precision(P, torch, K, x, ws, steps):
             y = step(P, K, x, y, ws, 0, comp)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
-        out[comp] = dict(ms_per_step=round(1e3 * dt, 3),
-                         rel_err_vs_f64_gpu=float("%.3e" % rel_diff(P, y, y64)))
+        err = rel_diff(P, y, y64)
+        out[comp] = dict(ms_per_step=round(1e3 * dt, 3), rel_err_vs_f64_gpu=float("%.3e" % err),
+                         within_metric_tolerance=bool(err <= MIXED_TOL))
     return out
 
 
