@@ -251,11 +251,34 @@ def batched_steps(P, torch, ncases: int):
         torch.cuda.synchronize()
         rates[nw] = time.perf_counter() - t0
     best = min(rates, key=rates.get)
+    ref = [(list(y.ranks), c.norm) for y, c in zip(batch.outputs(), batch.cases)]
+    # the same batch as one HIP graph (qtt_matvec_round_graph_*): one launch
+    # per replay, the cases split over independent branches
+    grates, same = {}, True
+    for nb in (1, 8, 32):
+        g = P.StepGraph(batch, nb)
+        try:
+            g.launch()                          # first replay: warm-up
+            g.collect()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.launch()
+            g.collect()
+            grates[nb] = time.perf_counter() - t0
+            same = same and all(list(y.ranks) == r and abs(c.norm - n) <= 1e-12 * abs(n)
+                                for y, c, (r, n) in zip(batch.outputs(), batch.cases, ref))
+        finally:
+            g.close()
+    gbest = min(grates, key=grates.get)
     levels = sorted(set(W.batch_case(i).level for i in range(ncases)))
     return dict(cases=ncases, levels=levels, best_workers=best,
                 steps_per_s={str(k): round(ncases / v, 2) for k, v in rates.items()},
                 gbs_at_best=round(nbytes / rates[best] / 1e9, 2),
-                speedup_vs_1_worker=round(rates[1] / rates[best], 2))
+                speedup_vs_1_worker=round(rates[1] / rates[best], 2),
+                graph_steps_per_s={str(k): round(ncases / v, 2) for k, v in grates.items()},
+                graph_best_branches=gbest,
+                graph_vs_best_workers=round(rates[best] / grates[gbest], 2),
+                graph_equals_workers=bool(same))
 
 
 def batched_solves(P, torch, ncases: int, chunk: int = 32, ntune: int = 16):

@@ -449,6 +449,43 @@ qtt_status qtt_matvec_round_batched(int32_t n, qtt_matvec_round_case *cases, int
                                     void *const *ws, const size_t *ws_bytes,
                                     void *const *streams);
 
+/* The batched hot step as one HIP graph.  The launches of n independent
+ * steps y_i = round(A_i x_i) (each exactly the launch sequence of
+ * qtt_matvec_round, Sec. 4's product and TT rounding) are captured once
+ * into a graph of `nbranch` independent branches; each replay runs the
+ * whole batch with one hipGraphLaunch and no host synchronisation.
+ *
+ * qtt_matvec_round_graph_aux_bytes — bytes of the device buffer `aux` that
+ *   receives every case's ranks and (norm, squared error).
+ * qtt_matvec_round_graph_create — validates every case as qtt_matvec_round
+ *   does, and y_i's capacity against the largest ranks the rounding can
+ *   leave (the product ranks capped by rmax); assigns the cases to branches
+ *   (largest workspace first, least loaded branch), branch b running its
+ *   cases in sequence in ws[b] (ws_bytes[b] bytes, enough for each of them:
+ *   qtt_matvec_round_workspace); captures and instantiates the graph.  The
+ *   graph keeps the addresses of A_i, x_i, y_i (data and d_ranks), the
+ *   workspaces and aux, and the ranks of A_i and x_i and the scalars of
+ *   each case as they are now: all must stay allocated, and a change of a
+ *   rank or scalar needs a new graph.  Refused while qtt_kernel_timing is
+ *   on.  Uses streams of its own for the capture; enqueues nothing.
+ * qtt_matvec_round_graph_launch — enqueues one replay on `stream`: y_i's
+ *   data and device ranks (d_ranks, when set) are written, host ranks are
+ *   not.  Replays that overlap in time race on the workspaces.
+ * qtt_matvec_round_graph_collect — synchronises `stream` (the one of the
+ *   last replay) and writes y_i's host ranks and cases[i].norm, .err and
+ *   .status (cases: the array of n given at creation, or a copy of it).
+ * qtt_matvec_round_graph_destroy — frees the graph (NULL is a no-op).    */
+typedef struct qtt_graph qtt_graph;
+qtt_status qtt_matvec_round_graph_aux_bytes(int32_t n, size_t *bytes);
+qtt_status qtt_matvec_round_graph_create(int32_t n, const qtt_matvec_round_case *cases,
+                                         int32_t nbranch, void *const *ws,
+                                         const size_t *ws_bytes, void *aux, size_t aux_bytes,
+                                         qtt_graph **out);
+qtt_status qtt_matvec_round_graph_launch(qtt_graph *g, void *stream);
+qtt_status qtt_matvec_round_graph_collect(qtt_graph *g, qtt_matvec_round_case *cases,
+                                          void *stream);
+qtt_status qtt_matvec_round_graph_destroy(qtt_graph *g);
+
 /* ------------------------------------------------------------ warm start */
 /* A multilayer perceptron from load parameters to the QTT cores of the
  * displacement (the learned warm start of the solve; not in the paper).

@@ -9,6 +9,6 @@ from ._lib import (  # noqa: F401
     LIB_PATH, QttError, TT, Problem, SolveOpts, lib, load_library,
     matvec, matvec_round, matvec_round_workspace, round_, round_sketch, dot, dot_noalloc, kernel_timing, kernel_timing_read, tt_combine, tt_align, tt_contract_last, axpby, assemble, assemble_bpx, solve, solve_workspace_bytes,
     tt_from_cores, tt_to_cores, problem_from_workload, version,
-    Batch, solve_batched, autotune_batched, StepBatch, matvec_round_batched,
+    Batch, solve_batched, autotune_batched, StepBatch, StepGraph, matvec_round_batched,
     MLP, columns, tt_from_packed,
 )

@@ -148,6 +148,12 @@ def load_library(path: str = LIB_PATH):
     L.qtt_matvec_round_batched.argtypes = [C.c_int32, P(_MVRCase), C.c_int32, P(vp), P(sz),
                                            P(vp)]
     L.qtt_autotune_batched.argtypes = [C.c_int32, P(_SolveCase), P(C.c_int32), P(C.c_double)]
+    L.qtt_matvec_round_graph_aux_bytes.argtypes = [C.c_int32, P(sz)]
+    L.qtt_matvec_round_graph_create.argtypes = [C.c_int32, P(_MVRCase), C.c_int32, P(vp), P(sz),
+                                                vp, sz, P(vp)]
+    L.qtt_matvec_round_graph_launch.argtypes = [vp, vp]
+    L.qtt_matvec_round_graph_collect.argtypes = [vp, P(_MVRCase), vp]
+    L.qtt_matvec_round_graph_destroy.argtypes = [vp]
     for name in ("qtt_matvec", "qtt_round", "qtt_round_workspace", "qtt_round_sketch",
                  "qtt_round_sketch_workspace", "qtt_matvec_round", "qtt_matvec_round_workspace",
                  "qtt_dot", "qtt_dot_noalloc", "qtt_axpby", "qtt_kernel_timing", "qtt_tt_combine",
@@ -156,7 +162,9 @@ def load_library(path: str = LIB_PATH):
                  "qtt_assemble_stiffness", "qtt_assemble_workspace", "qtt_assemble_bpx", "qtt_solve",
                  "qtt_solve_workspace", "qtt_solve_batched", "qtt_autotune_batched",
                  "qtt_matvec_round_batched", "qtt_warmstart_workspace", "qtt_warmstart_infer",
-                 "qtt_warmstart_train_step"):
+                 "qtt_warmstart_train_step", "qtt_matvec_round_graph_aux_bytes",
+                 "qtt_matvec_round_graph_create", "qtt_matvec_round_graph_launch",
+                 "qtt_matvec_round_graph_collect", "qtt_matvec_round_graph_destroy"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -647,6 +655,51 @@ def matvec_round_batched(batch: StepBatch):
     _check(lib().qtt_matvec_round_batched(batch.n, batch.cases, batch.nworkers, batch.ws_ptr,
                                           batch.ws_len, batch.st_ptr))
     return batch.outputs()
+
+
+class StepGraph:
+    """The batch's hot steps captured into one HIP graph
+    (qtt_matvec_round_graph_*): `nbranch` independent branches, branch b
+    running its cases in sequence in the batch's workspace b.  launch()
+    enqueues one replay; collect() waits for it and sets the outputs' ranks
+    and the cases' norm and err.  The graph holds the batch's buffers, so the
+    batch must outlive it."""
+
+    def __init__(self, batch: StepBatch, nbranch: int):
+        torch = _torch()
+        batch.set_workers(nbranch)
+        self.batch = batch
+        n = C.c_size_t()
+        _check(lib().qtt_matvec_round_graph_aux_bytes(batch.n, C.byref(n)))
+        self._aux = _workspace(n.value)
+        h = C.c_void_p()
+        torch.cuda.synchronize()
+        _check(lib().qtt_matvec_round_graph_create(batch.n, batch.cases, nbranch, batch.ws_ptr,
+                                                   batch.ws_len, _aligned_ptr(self._aux),
+                                                   self._aux.numel() - 256, C.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        torch = _torch()
+        st = (stream or torch.cuda.current_stream()).cuda_stream
+        _check(lib().qtt_matvec_round_graph_launch(self.handle, st))
+
+    def collect(self, stream=None):
+        torch = _torch()
+        st = (stream or torch.cuda.current_stream()).cuda_stream
+        _check(lib().qtt_matvec_round_graph_collect(self.handle, self.batch.cases, st))
+        return self.batch.outputs()
+
+    def close(self):
+        if self.handle:
+            _check(lib().qtt_matvec_round_graph_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class MLP:

@@ -29,6 +29,7 @@ SOURCES = [
     "k_als.hip",
     "k_full.hip",
     "batched.cpp",
+    "graph.cpp",
     "k_mlp.hip",
     "noalloc.cpp",
     "ktimer.cpp",

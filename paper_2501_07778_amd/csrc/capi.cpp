@@ -327,6 +327,57 @@ static bool carve_matvec_round(Arena &ar, const qtt_tt *A, const qtt_tt *x, int3
   return ar.ok();
 }
 
+}  // extern "C"
+
+// every argument check of qtt_matvec_round except the workspace's size
+qtt_status qtt::check_matvec_round_args(const qtt_tt *A, const qtt_tt *x, const qtt_tt *y,
+                                   qtt_dtype compute, int32_t ell, double eps) {
+  qtt_status st;
+  if ((st = check_matvec_args(A, x, compute)) != QTT_OK) return st;
+  if (!y || !y->ranks || !y->nrow || !y->data) return fail(QTT_E_INVAL, "y: NULL field");
+  if (y->ncores != A->ncores || y->ncol) return fail(QTT_E_SHAPE, "y must be a vector like x");
+  for (int k = 0; k < A->ncores; ++k)
+    if (y->nrow[k] != A->nrow[k]) return fail(QTT_E_SHAPE, "y mode != A row mode");
+  if (ell < 0 || ell > 512) return fail(QTT_E_INVAL, "ell must be in 0..512");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(QTT_E_INVAL, "eps must be >= 0");
+  return QTT_OK;
+}
+
+// Carves the step's buffers from ws and enqueues every launch of the step
+// on s up to the rounded train in the workspace (device ranks p.t.v.rk,
+// norm and squared error in p.w.scal): the ranks of A and x travel as
+// kernel arguments, so the sequence holds no host synchronisation, no
+// host-to-device copy and no memset, and can be captured into a graph.
+qtt_status qtt::enqueue_matvec_round(const qtt_tt *A, const qtt_tt *x, qtt_dtype compute,
+                                int32_t ell, uint64_t seed, double eps, int32_t rmax, void *ws,
+                                size_t ws_bytes, hipStream_t s, MatvecRoundPlan &p) {
+  Arena ar;
+  ar.base = (char *)ws;
+  ar.size = ws_bytes;
+  double *sk;
+  int32_t *rk;
+  if (!carve_matvec_round(ar, A, x, ell, p.t, p.w, sk, rk))
+    return fail(QTT_E_CAPACITY, "workspace too small for qtt_matvec_round: need " +
+                                    std::to_string(ar.used));
+  TTView va, vx;
+  packed_view(A, va, rk);
+  packed_view(x, vx, rk + (QTT_MAXD + 1));
+  QTT_HIP(upload_ranks(va, A->ranks, s));
+  QTT_HIP(upload_ranks(vx, x->ranks, s));
+  // the product goes straight into the slotted train (the kernel writes its
+  // device ranks), then sketch and rounding work on it in place
+  QTT_HIP(launch_matvec(va, vx, p.t.v, compute, s));
+  if (ell > 0) {
+    QTT_HIP(sketch_tt(p.t.v, ell, seed, 0, sk, s));
+    QTT_HIP(round_tt(p.t.v, eps, rmax, p.w, s, true, ell));
+  } else {
+    QTT_HIP(round_tt(p.t.v, eps, rmax, p.w, s));
+  }
+  return QTT_OK;
+}
+
+extern "C" {
+
 qtt_status qtt_matvec_round_workspace(const qtt_tt *A, const qtt_tt *x, int32_t ell,
                                       size_t *bytes) {
   qtt_status st;
@@ -349,51 +400,26 @@ qtt_status qtt_matvec_round(const qtt_tt *A, const qtt_tt *x, qtt_tt *y, qtt_dty
                             double *err, void *ws, size_t ws_bytes, void *stream) {
   qtt::clear_stale_error();
   qtt_status st;
-  if ((st = check_matvec_args(A, x, compute)) != QTT_OK) return st;
-  if (!y || !y->ranks || !y->nrow || !y->data) return fail(QTT_E_INVAL, "y: NULL field");
-  if (y->ncores != A->ncores || y->ncol) return fail(QTT_E_SHAPE, "y must be a vector like x");
-  for (int k = 0; k < A->ncores; ++k)
-    if (y->nrow[k] != A->nrow[k]) return fail(QTT_E_SHAPE, "y mode != A row mode");
-  if (ell < 0 || ell > 512) return fail(QTT_E_INVAL, "ell must be in 0..512");
-  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(QTT_E_INVAL, "eps must be >= 0");
+  if ((st = check_matvec_round_args(A, x, y, compute, ell, eps)) != QTT_OK) return st;
   if (!ws) return fail(QTT_E_CAPACITY, "workspace is NULL");
-  Arena ar;
-  ar.base = (char *)ws;
-  ar.size = ws_bytes;
-  TTDesc t;
-  RoundWs w;
-  double *sk;
-  int32_t *rk;
-  if (!carve_matvec_round(ar, A, x, ell, t, w, sk, rk))
-    return fail(QTT_E_CAPACITY, "workspace too small for qtt_matvec_round: need " +
-                                    std::to_string(ar.used));
   const int D = A->ncores;
   hipStream_t s = (hipStream_t)stream;
-  TTView va, vx;
-  packed_view(A, va, rk);
-  packed_view(x, vx, rk + (QTT_MAXD + 1));
-  QTT_HIP(upload_ranks(va, A->ranks, s));
-  QTT_HIP(upload_ranks(vx, x->ranks, s));
-  // the product goes straight into the slotted train (the kernel writes its
-  // device ranks), then sketch and rounding work on it in place
-  QTT_HIP(launch_matvec(va, vx, t.v, compute, s));
-  if (ell > 0) {
-    QTT_HIP(sketch_tt(t.v, ell, seed, 0, sk, s));
-    QTT_HIP(round_tt(t.v, eps, rmax, w, s, true, ell));
-  } else {
-    QTT_HIP(round_tt(t.v, eps, rmax, w, s));
-  }
+  MatvecRoundPlan p;
+  if ((st = enqueue_matvec_round(A, x, compute, ell, seed, eps, rmax, ws, ws_bytes, s, p)) !=
+      QTT_OK)
+    return st;
   int32_t rk_host[QTT_MAXD + 1];
   double scal[2];
-  QTT_HIP(hipMemcpyAsync(rk_host, t.v.rk, sizeof(int32_t) * (D + 1), hipMemcpyDeviceToHost, s));
-  QTT_HIP(hipMemcpyAsync(scal, w.scal, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+  QTT_HIP(hipMemcpyAsync(rk_host, p.t.v.rk, sizeof(int32_t) * (D + 1), hipMemcpyDeviceToHost,
+                         s));
+  QTT_HIP(hipMemcpyAsync(scal, p.w.scal, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
   QTT_HIP(hipStreamSynchronize(s));
   int64_t need = 0;
   for (int k = 0; k < D; ++k) need += (int64_t)rk_host[k] * y->nrow[k] * rk_host[k + 1];
   if (need > y->capacity)
     return fail(QTT_E_CAPACITY, "y: capacity " + std::to_string(y->capacity) + " < " +
                                     std::to_string(need));
-  QTT_HIP(launch_pack(t.v, (double *)y->data, s));
+  QTT_HIP(launch_pack(p.t.v, (double *)y->data, s));
   QTT_HIP(hipStreamSynchronize(s));
   for (int k = 0; k <= D; ++k) y->ranks[k] = rk_host[k];
   QTT_HIP(publish_ranks(y, s));

@@ -1,0 +1,223 @@
+// The batched hot step as one HIP graph: the launches of n independent
+// y_i = round(A_i x_i) captured once, split over branches that share
+// nothing (each branch its own workspace, its cases in sequence), and
+// replayed by one hipGraphLaunch.  The step holds no host synchronisation
+// (device-side ranks, kernel-argument rank uploads, the capacity of y
+// checked at capture against the bound its ranks can reach), so the whole
+// batch is one launch and the host only reads back ranks and norms.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "internal.h"
+
+struct qtt_graph {
+  int n = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<qtt_tt *> y;  // outputs, for the host ranks at collect
+  int32_t *aux_rk = nullptr;
+  double *aux_scal = nullptr;
+};
+
+namespace qtt {
+namespace {
+
+constexpr size_t kRkStride = QTT_MAXD + 1;  // int32 per case
+
+size_t aux_bytes_of(int n) {
+  return ((sizeof(int32_t) * kRkStride * n + 255) & ~size_t(255)) + sizeof(double) * 2 * n;
+}
+
+// packed elements of y at the largest ranks the rounding can leave: the
+// product ranks, capped by rmax when it is positive
+int64_t y_bound(const qtt_tt *A, const qtt_tt *x, int32_t rmax) {
+  const int D = A->ncores;
+  std::vector<int64_t> b(D + 1);
+  for (int k = 0; k <= D; ++k) {
+    int64_t r = (int64_t)A->ranks[k] * x->ranks[k];
+    b[k] = (rmax > 0 && r > rmax) ? rmax : r;
+  }
+  int64_t e = 0;
+  for (int k = 0; k < D; ++k) e += b[k] * A->nrow[k] * b[k + 1];
+  return e;
+}
+
+struct Streams {
+  std::vector<hipStream_t> s;
+  std::vector<hipEvent_t> e;
+  ~Streams() {
+    for (auto x : e) (void)hipEventDestroy(x);
+    for (auto x : s) (void)hipStreamDestroy(x);
+  }
+};
+
+}  // namespace
+}  // namespace qtt
+
+using namespace qtt;
+
+extern "C" {
+
+qtt_status qtt_matvec_round_graph_aux_bytes(int32_t n, size_t *bytes) {
+  if (n < 1) return fail(QTT_E_INVAL, "n must be >= 1");
+  if (!bytes) return fail(QTT_E_INVAL, "bytes is NULL");
+  *bytes = aux_bytes_of(n);
+  return QTT_OK;
+}
+
+qtt_status qtt_matvec_round_graph_create(int32_t n, const qtt_matvec_round_case *cases,
+                                         int32_t nbranch, void *const *ws,
+                                         const size_t *ws_bytes, void *aux, size_t aux_bytes,
+                                         qtt_graph **out) {
+  qtt::clear_stale_error();
+  if (!out) return fail(QTT_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || !cases) return fail(QTT_E_INVAL, "need n >= 1 cases");
+  if (nbranch < 1 || nbranch > 64 || !ws || !ws_bytes)
+    return fail(QTT_E_INVAL, "nbranch must be in 1..64 with a workspace each");
+  for (int b = 0; b < nbranch; ++b)
+    if (!ws[b]) return fail(QTT_E_INVAL, "NULL branch workspace");
+  if (!aux || aux_bytes < aux_bytes_of(n) || ((uintptr_t)aux & 255))
+    return fail(QTT_E_CAPACITY, "aux: need " + std::to_string(aux_bytes_of(n)) +
+                                    " bytes, 256-byte aligned");
+  if (ktimer_active())
+    return fail(QTT_E_INVAL, "kernel timing is on: its event records cannot be captured");
+  // every check of the eager step, and y's capacity against the ranks the
+  // rounding can reach (the replay cannot stop to look at them)
+  std::vector<size_t> need(n);
+  for (int i = 0; i < n; ++i) {
+    const qtt_matvec_round_case &c = cases[i];
+    qtt_status st = check_matvec_round_args(c.A, c.x, c.y, c.compute, c.ell, c.eps);
+    if (st != QTT_OK)
+      return fail(st, "case " + std::to_string(i) + ": " + std::string(qtt_last_error()));
+    const int64_t yb = y_bound(c.A, c.x, c.rmax);
+    if (yb > c.y->capacity)
+      return fail(QTT_E_CAPACITY, "case " + std::to_string(i) + ": y capacity " +
+                                      std::to_string(c.y->capacity) + " < " +
+                                      std::to_string(yb) + " (ranks capped by rmax)");
+    if ((st = qtt_matvec_round_workspace(c.A, c.x, c.ell, &need[i])) != QTT_OK) return st;
+  }
+  // longest case first onto the least loaded branch; a branch's workspace
+  // must hold the largest of its cases
+  std::vector<int> order(n), branch(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return need[a] > need[b]; });
+  std::vector<double> load(nbranch, 0.0);
+  for (int i : order) {
+    const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    branch[i] = b;
+    load[b] += (double)need[i];
+    if (need[i] > ws_bytes[b])
+      return fail(QTT_E_CAPACITY, "branch workspace " + std::to_string(b) + ": " +
+                                      std::to_string(ws_bytes[b]) + " < " +
+                                      std::to_string(need[i]) + " bytes for case " +
+                                      std::to_string(i));
+  }
+  // capture: the origin stream forks to one stream per branch and joins them
+  Streams st;
+  st.s.resize(nbranch + 1, nullptr);
+  st.e.resize(nbranch + 1, nullptr);
+  for (int b = 0; b <= nbranch; ++b) {
+    QTT_HIP(hipStreamCreateWithFlags(&st.s[b], hipStreamNonBlocking));
+    QTT_HIP(hipEventCreateWithFlags(&st.e[b], hipEventDisableTiming));
+  }
+  hipStream_t s0 = st.s[nbranch];
+  int32_t *aux_rk = (int32_t *)aux;
+  double *aux_scal = (double *)((char *)aux + ((sizeof(int32_t) * kRkStride * n + 255) &
+                                               ~size_t(255)));
+  QTT_HIP(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+  qtt_status cst = QTT_OK;
+  auto capture = [&]() -> qtt_status {
+    QTT_HIP(hipEventRecord(st.e[nbranch], s0));
+    for (int b = 0; b < nbranch; ++b) {
+      hipStream_t sb = st.s[b];
+      QTT_HIP(hipStreamWaitEvent(sb, st.e[nbranch], 0));
+      for (int i : order) {
+        if (branch[i] != b) continue;
+        const qtt_matvec_round_case &c = cases[i];
+        MatvecRoundPlan p;
+        qtt_status r = enqueue_matvec_round(c.A, c.x, c.compute, c.ell, c.seed, c.eps, c.rmax,
+                                            ws[b], ws_bytes[b], sb, p);
+        if (r != QTT_OK) return r;
+        QTT_HIP(launch_pack(p.t.v, (double *)c.y->data, sb));
+        QTT_HIP(launch_step_result(p.t.v, p.w.scal, aux_rk + kRkStride * i, aux_scal + 2 * i,
+                                   c.y->d_ranks, sb));
+      }
+      QTT_HIP(hipEventRecord(st.e[b], sb));
+      QTT_HIP(hipStreamWaitEvent(s0, st.e[b], 0));
+    }
+    return QTT_OK;
+  };
+  cst = capture();
+  hipGraph_t graph = nullptr;
+  hipError_t ec = hipStreamEndCapture(s0, &graph);
+  if (cst != QTT_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return cst;
+  }
+  if (ec != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(QTT_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+  }
+  hipGraphExec_t exec = nullptr;
+  ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ec != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(QTT_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ec));
+  }
+  qtt_graph *g = new qtt_graph;
+  g->n = n;
+  g->graph = graph;
+  g->exec = exec;
+  g->aux_rk = aux_rk;
+  g->aux_scal = aux_scal;
+  g->y.resize(n);
+  for (int i = 0; i < n; ++i) g->y[i] = cases[i].y;
+  *out = g;
+  return QTT_OK;
+}
+
+qtt_status qtt_matvec_round_graph_launch(qtt_graph *g, void *stream) {
+  qtt::clear_stale_error();
+  if (!g || !g->exec) return fail(QTT_E_INVAL, "graph is NULL");
+  QTT_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return QTT_OK;
+}
+
+qtt_status qtt_matvec_round_graph_collect(qtt_graph *g, qtt_matvec_round_case *cases,
+                                          void *stream) {
+  qtt::clear_stale_error();
+  if (!g || !g->exec) return fail(QTT_E_INVAL, "graph is NULL");
+  if (!cases) return fail(QTT_E_INVAL, "cases is NULL");
+  const int n = g->n;
+  std::vector<int32_t> rk(kRkStride * n);
+  std::vector<double> sc(2 * n);
+  hipStream_t s = (hipStream_t)stream;
+  QTT_HIP(hipMemcpyAsync(rk.data(), g->aux_rk, sizeof(int32_t) * rk.size(),
+                         hipMemcpyDeviceToHost, s));
+  QTT_HIP(hipMemcpyAsync(sc.data(), g->aux_scal, sizeof(double) * sc.size(),
+                         hipMemcpyDeviceToHost, s));
+  QTT_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < n; ++i) {
+    qtt_tt *y = g->y[i];
+    for (int k = 0; k <= y->ncores; ++k) y->ranks[k] = rk[kRkStride * i + k];
+    cases[i].norm = sc[2 * i];
+    cases[i].err = std::sqrt(sc[2 * i + 1] > 0.0 ? sc[2 * i + 1] : 0.0);
+    cases[i].status = QTT_OK;
+  }
+  return QTT_OK;
+}
+
+qtt_status qtt_matvec_round_graph_destroy(qtt_graph *g) {
+  if (!g) return QTT_OK;
+  hipError_t e1 = g->exec ? hipGraphExecDestroy(g->exec) : hipSuccess;
+  hipError_t e2 = g->graph ? hipGraphDestroy(g->graph) : hipSuccess;
+  delete g;
+  if (e1 != hipSuccess || e2 != hipSuccess)
+    return fail(QTT_E_HIP, "hipGraph destroy failed");
+  return QTT_OK;
+}
+
+}  // extern "C"

@@ -44,6 +44,11 @@ int ktimer_begin(int id, hipStream_t s) {
   return (int)g_recs.size() - 1;
 }
 
+bool ktimer_active() {
+  std::lock_guard<std::mutex> g(g_mu);
+  return g_on;
+}
+
 void ktimer_end(int handle, hipStream_t s) {
   if (handle < 0) return;
   std::lock_guard<std::mutex> g(g_mu);

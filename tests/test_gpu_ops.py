@@ -249,6 +249,61 @@ def test_matvec_round_batched_equals_single(P):
         assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b)
 
 
+@pytest.mark.parametrize("nbranch", [1, 4])
+def test_matvec_round_graph_equals_single(P, nbranch):
+    """The batch of hot steps captured into one HIP graph (cases on `nbranch`
+    branches) gives, on every replay, the ranks, trains, norms and errors of
+    the same steps run one at a time.  Between replays the outputs are
+    overwritten with NaN and other eager work runs on the same stream, so
+    each replay is checked on what it wrote itself."""
+    import torch
+    from oracle import assembly as A
+    items = []
+    for i, (d, r) in enumerate([(4, 8), (5, 12), (3, 5), (6, 16), (5, 7), (4, 3)]):
+        Kq, _ = A.assemble_qtt(W.cantilever_traction(d))
+        modes = [2] * (2 * d + 1)
+        x = W.random_tt_cores(20 + i, modes, W.capped_ranks(modes, r))
+        items.append((P.tt_from_cores(Kq), P.tt_from_cores(x), 24 if i % 2 else 0, 7 + i,
+                      1e-8, 20, "f64"))
+    ref = [P.matvec_round(K, x, ell, seed, eps, rmax, comp)
+           for (K, x, ell, seed, eps, rmax, comp) in items]
+    batch = P.StepBatch(items, nbranch)
+    g = P.StepGraph(batch, nbranch)
+    try:
+        for rep in range(3):
+            for y in batch.outputs():
+                y.data.fill_(float("nan"))
+            g.launch()
+            K, x, ell, seed, eps, rmax, comp = items[rep]
+            P.matvec_round(K, x, ell, seed + 100, eps, rmax, comp)  # eager work between
+            outs = g.collect()
+            for i, ((y1, n1, e1), y) in enumerate(zip(ref, outs)):
+                assert y.ranks == y1.ranks, (rep, i)
+                a = T.full_vector(P.tt_to_cores(y))
+                b = T.full_vector(P.tt_to_cores(y1))
+                assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b), (rep, i)
+                assert batch.cases[i].norm == pytest.approx(n1, rel=1e-13)
+                assert batch.cases[i].err == pytest.approx(e1, rel=1e-9, abs=1e-13 * n1)
+                assert batch.cases[i].status == 0
+    finally:
+        g.close()
+    torch.cuda.synchronize()
+
+
+def test_matvec_round_graph_refuses_small_output(P):
+    """A y whose capacity is below the ranks the rounding may leave is refused
+    when the graph is built (the replay cannot check it)."""
+    from oracle import assembly as A
+    Kq, _ = A.assemble_qtt(W.cantilever_traction(4))
+    modes = [2] * 9
+    x = W.random_tt_cores(3, modes, W.capped_ranks(modes, 6))
+    batch = P.StepBatch([(P.tt_from_cores(Kq), P.tt_from_cores(x), 0, 1, 1e-8, 20, "f64")], 1)
+    y = batch.outputs()[0]
+    y.c.capacity = 10
+    with pytest.raises(P.QttError):
+        P.StepGraph(batch, 1)
+
+
 def _diff_norm(a, b):
     """||a - b|| of two TT vectors from the oracle: the difference train
     (core concatenation) orthogonalised left to right, whose last core
