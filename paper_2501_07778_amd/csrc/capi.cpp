@@ -4,7 +4,7 @@
 #include <cstring>
 #include <string>
 
-#include "internal.h"
+#include "step.h"
 
 namespace qtt {
 
@@ -329,7 +329,6 @@ static bool carve_matvec_round(Arena &ar, const qtt_tt *A, const qtt_tt *x, int3
 
 }  // extern "C"
 
-// every argument check of qtt_matvec_round except the workspace's size
 qtt_status qtt::check_matvec_round_args(const qtt_tt *A, const qtt_tt *x, const qtt_tt *y,
                                    qtt_dtype compute, int32_t ell, double eps) {
   qtt_status st;
@@ -343,11 +342,6 @@ qtt_status qtt::check_matvec_round_args(const qtt_tt *A, const qtt_tt *x, const 
   return QTT_OK;
 }
 
-// Carves the step's buffers from ws and enqueues every launch of the step
-// on s up to the rounded train in the workspace (device ranks p.t.v.rk,
-// norm and squared error in p.w.scal): the ranks of A and x travel as
-// kernel arguments, so the sequence holds no host synchronisation, no
-// host-to-device copy and no memset, and can be captured into a graph.
 qtt_status qtt::enqueue_matvec_round(const qtt_tt *A, const qtt_tt *x, qtt_dtype compute,
                                 int32_t ell, uint64_t seed, double eps, int32_t rmax, void *ws,
                                 size_t ws_bytes, hipStream_t s, MatvecRoundPlan &p) {

@@ -10,7 +10,7 @@
 #include <numeric>
 #include <vector>
 
-#include "internal.h"
+#include "step.h"
 
 struct qtt_graph {
   int n = 0;
@@ -42,6 +42,25 @@ int64_t y_bound(const qtt_tt *A, const qtt_tt *x, int32_t rmax) {
   int64_t e = 0;
   for (int k = 0; k < D; ++k) e += b[k] * A->nrow[k] * b[k + 1];
   return e;
+}
+
+// the rounded train's ranks and (norm, squared error) into the case's
+// slots of aux, and the ranks into y's device mirror when it has one
+__global__ void k_step_result(const int *rk, int D, const double *scal, int *out_rk,
+                              double *out_scal, int *d_ranks) {
+  const int i = threadIdx.x;
+  if (i <= D) {
+    out_rk[i] = rk[i];
+    if (d_ranks) d_ranks[i] = rk[i];
+  }
+  if (i < 2) out_scal[i] = scal[i];
+}
+
+hipError_t launch_step_result(const TTView &t, const double *scal, int32_t *out_rk,
+                              double *out_scal, int32_t *d_ranks, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_result, dim3(1), dim3(64), 0, s, t.rk, t.D, scal, out_rk,
+                     out_scal, d_ranks);
+  return hipGetLastError();
 }
 
 struct Streams {

@@ -174,25 +174,6 @@ hipError_t tt_full(const TTView &v, const int32_t *rk, double *out, double *ws,
 hipError_t launch_diff_norm2(const double *a, const double *b, int64_t n, double *out,
                              hipStream_t s);
 
-// ---------------------------------------------------------------- hot step
-// The launches of qtt_matvec_round (capi.cpp), shared by the graph form
-// (graph.cpp): the product train and rounding workspace carved from ws.
-struct MatvecRoundPlan {
-  TTDesc t;
-  RoundWs w;
-};
-qtt_status check_matvec_round_args(const qtt_tt *A, const qtt_tt *x, const qtt_tt *y,
-                                   qtt_dtype compute, int32_t ell, double eps);
-qtt_status enqueue_matvec_round(const qtt_tt *A, const qtt_tt *x, qtt_dtype compute,
-                                int32_t ell, uint64_t seed, double eps, int32_t rmax, void *ws,
-                                size_t ws_bytes, hipStream_t s, MatvecRoundPlan &p);
-// copies the rounded train's ranks and (norm, squared error) into out_rk and
-// out_scal, and the ranks into d_ranks when it is not NULL (one thread block)
-hipError_t launch_step_result(const TTView &t, const double *scal, int32_t *out_rk,
-                              double *out_scal, int32_t *d_ranks, hipStream_t s);
-// true while qtt_kernel_timing records events
-bool ktimer_active();
-
 // fills the device ranks from a host array
 hipError_t upload_ranks(const TTView &v, const int32_t *ranks,
                         hipStream_t s);

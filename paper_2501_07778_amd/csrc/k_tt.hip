@@ -711,25 +711,6 @@ __global__ void k_set_ranks(int *rk, RankArg a) {
 }
 }  // namespace
 
-namespace {
-__global__ void k_step_result(const int *rk, int D, const double *scal, int *out_rk,
-                              double *out_scal, int *d_ranks) {
-  const int i = threadIdx.x;
-  if (i <= D) {
-    out_rk[i] = rk[i];
-    if (d_ranks) d_ranks[i] = rk[i];
-  }
-  if (i < 2) out_scal[i] = scal[i];
-}
-}  // namespace
-
-hipError_t launch_step_result(const TTView &t, const double *scal, int32_t *out_rk,
-                              double *out_scal, int32_t *d_ranks, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_result, dim3(1), dim3(64), 0, s, t.rk, t.D, scal, out_rk,
-                     out_scal, d_ranks);
-  return hipGetLastError();
-}
-
 // ranks travel as a kernel argument, so the host array may be reused at once
 hipError_t upload_ranks(const TTView &v, const int32_t *ranks,
                         hipStream_t s) {

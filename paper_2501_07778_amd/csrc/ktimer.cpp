@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "internal.h"
+#include "step.h"
 
 namespace qtt {
 namespace {
