@@ -495,7 +495,9 @@ def learned_start(P, torch, level: int, ntrain: int, nheld: int, epochs: int):
     held = np.stack([W.warmstart_params(s) for s in range(4096, 4096 + nheld)], axis=1)
     sopts = P.SolveOpts(tol=1e-6, eps=1e-6, rmax=32, rmax_in=8, maxit_out=40, method="als",
                         seed=1)
-    rows = LS.compare_starts(net, W.cantilever_two_component, level, held, nrow, ranks, sopts)
+    rows = LS.compare_starts(net, W.cantilever_two_component, level, held, nrow, ranks, sopts,
+                             progress=lambda j: note("learned start: %d held-out loads" % j),
+                             keep_solutions=False)
     ok = [r for r in rows if r["warm_status"] == 0 and r["cold_status"] == 0]
     med = lambda v: float(np.median(v)) if v else None
     tw = sum(r["warm_s"] for r in rows)
@@ -510,6 +512,12 @@ def learned_start(P, torch, level: int, ntrain: int, nheld: int, epochs: int):
                 sweeps_mean_cold=round(float(np.mean([r["cold_sweeps"] for r in rows])), 2),
                 solves_per_s_warm=round(nheld / tw, 3), solves_per_s_cold=round(nheld / tc, 3),
                 speedup=round(tc / tw, 3), converged_both=len(ok),
+                sweeps_median_warm=med([r["warm_sweeps"] for r in rows]),
+                sweeps_median_cold=med([r["cold_sweeps"] for r in rows]),
+                fewer_sweeps_frac=round(sum(1 for r in rows if r["warm_sweeps"] < r["cold_sweeps"])
+                                        / max(nheld, 1), 3),
+                more_sweeps_frac=round(sum(1 for r in rows if r["warm_sweeps"] > r["cold_sweeps"])
+                                       / max(nheld, 1), 3),
                 fp64_residual_median_warm=float("%.3g" % med([r["warm_residual"] for r in rows])),
                 fp64_residual_median_cold=float("%.3g" % med([r["cold_residual"] for r in rows])),
                 **tm)

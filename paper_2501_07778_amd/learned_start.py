@@ -147,12 +147,13 @@ def init_params(sizes: Sequence[int], seed: int, out_bias: Optional[np.ndarray] 
 
 
 def compare_starts(net, problem_of, level: int, params: np.ndarray, nrow, ranks,
-                   opts: L.SolveOpts):
+                   opts: L.SolveOpts, progress=None, keep_solutions: bool = True):
     """Per held-out parameter vector: the solve from the network's start and
     the cold solve, with sweeps, seconds, FP64 residual and the difference
     of the two solutions.  The network's train is rounded exactly (eps 0,
     cap opts.rmax) to minimal ranks before the solve; that is part of the
-    warm time."""
+    warm time.  progress(j) is called after every 32nd load; with
+    keep_solutions False the rows hold no solution trains."""
     torch = L._torch()
     rows = []
     for j in range(params.shape[1]):
@@ -178,5 +179,8 @@ def compare_starts(net, problem_of, level: int, params: np.ndarray, nrow, ranks,
                          cold_residual=rc["residual"], warm_residual=rw["residual"],
                          warm_start=rw["warm_start"], warm_energy=rw["warm_energy"],
                          cold_status=rc["status"], warm_status=rw["status"],
-                         u_cold=uc, u_warm=uw))
+                         u_cold=uc if keep_solutions else None,
+                         u_warm=uw if keep_solutions else None))
+        if progress is not None and (j + 1) % 32 == 0:
+            progress(j + 1)
     return rows
