@@ -252,11 +252,12 @@ def batched_steps(P, torch, ncases: int):
         rates[nw] = time.perf_counter() - t0
     best = min(rates, key=rates.get)
     ref = [(list(y.ranks), c.norm) for y, c in zip(batch.outputs(), batch.cases)]
-    # the same batch as one HIP graph (qtt_matvec_round_graph_*): one launch
-    # per replay, the cases split over independent branches
-    grates, same = {}, True
-    for nb in (1, 8, 32):
-        g = P.StepGraph(batch, nb)
+    # the same batch as HIP graphs (qtt_matvec_round_graph_*), the cases split
+    # over independent branches: one graph (one launch per replay), or one
+    # graph per branch replayed on streams of its own
+    grates, prates, same = {}, {}, True
+    for nb, per in ((1, False), (8, False), (32, False), (8, True), (16, True), (32, True)):
+        g = P.StepGraph(batch, nb, per)
         try:
             g.launch()                          # first replay: warm-up
             g.collect()
@@ -264,7 +265,7 @@ def batched_steps(P, torch, ncases: int):
             t0 = time.perf_counter()
             g.launch()
             g.collect()
-            grates[nb] = time.perf_counter() - t0
+            (prates if per else grates)[nb] = time.perf_counter() - t0
             same = same and all(list(y.ranks) == r and abs(c.norm - n) <= 1e-12 * abs(n)
                                 for y, c, (r, n) in zip(batch.outputs(), batch.cases, ref))
         finally:
@@ -278,6 +279,9 @@ def batched_steps(P, torch, ncases: int):
                 graph_steps_per_s={str(k): round(ncases / v, 2) for k, v in grates.items()},
                 graph_best_branches=gbest,
                 graph_vs_best_workers=round(rates[best] / grates[gbest], 2),
+                branch_graphs_steps_per_s={str(k): round(ncases / v, 2)
+                                           for k, v in prates.items()},
+                branch_graphs_vs_best_workers=round(rates[best] / min(prates.values()), 2),
                 graph_equals_workers=bool(same))
 
 
@@ -529,9 +533,14 @@ def main():
         print("bench.py runs on one GPU only: the multi-GPU form (independent load cases "
               "per GPU) is not built", file=sys.stderr)
         sys.exit(2)
-    # concurrent streams of the batched measurement: one hardware queue each
-    # (HIP's default is 4 per process)
-    os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+    # concurrent streams of the batched measurement: one hardware queue each,
+    # up to 32 (HIP's default of 4 per process serialises the workers)
+    try:
+        nq = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+    except ValueError:
+        nq = 4
+    if nq < 32:
+        os.environ["GPU_MAX_HW_QUEUES"] = "32"
     import torch
     import paper_2501_07778_amd as P
 

@@ -452,8 +452,11 @@ qtt_status qtt_matvec_round_batched(int32_t n, qtt_matvec_round_case *cases, int
 /* The batched hot step as one HIP graph.  The launches of n independent
  * steps y_i = round(A_i x_i) (each exactly the launch sequence of
  * qtt_matvec_round, Sec. 4's product and TT rounding) are captured once
- * into a graph of `nbranch` independent branches; each replay runs the
- * whole batch with one hipGraphLaunch and no host synchronisation.
+ * into `nbranch` independent branches; each replay runs the whole batch
+ * with no host synchronisation: as one graph whose branches are parallel
+ * paths (per_branch = 0: one hipGraphLaunch), or as one graph per branch,
+ * each replayed on a stream of the handle's own, forked from the caller's
+ * stream and joined back into it by events (per_branch = 1).
  *
  * qtt_matvec_round_graph_aux_bytes — bytes of the device buffer `aux` that
  *   receives every case's ranks and (norm, squared error).
@@ -467,7 +470,8 @@ qtt_status qtt_matvec_round_batched(int32_t n, qtt_matvec_round_case *cases, int
  *   workspaces and aux, and the ranks of A_i and x_i and the scalars of
  *   each case as they are now: all must stay allocated, and a change of a
  *   rank or scalar needs a new graph.  Refused while qtt_kernel_timing is
- *   on.  Uses streams of its own for the capture; enqueues nothing.
+ *   on.  Captures on streams of its own (kept by the handle for the
+ *   per-branch replays); enqueues nothing.
  * qtt_matvec_round_graph_launch — enqueues one replay on `stream`: y_i's
  *   data and device ranks (d_ranks, when set) are written, host ranks are
  *   not.  Replays that overlap in time race on the workspaces.
@@ -480,7 +484,7 @@ qtt_status qtt_matvec_round_graph_aux_bytes(int32_t n, size_t *bytes);
 qtt_status qtt_matvec_round_graph_create(int32_t n, const qtt_matvec_round_case *cases,
                                          int32_t nbranch, void *const *ws,
                                          const size_t *ws_bytes, void *aux, size_t aux_bytes,
-                                         qtt_graph **out);
+                                         int32_t per_branch, qtt_graph **out);
 qtt_status qtt_matvec_round_graph_launch(qtt_graph *g, void *stream);
 qtt_status qtt_matvec_round_graph_collect(qtt_graph *g, qtt_matvec_round_case *cases,
                                           void *stream);

@@ -150,7 +150,7 @@ def load_library(path: str = LIB_PATH):
     L.qtt_autotune_batched.argtypes = [C.c_int32, P(_SolveCase), P(C.c_int32), P(C.c_double)]
     L.qtt_matvec_round_graph_aux_bytes.argtypes = [C.c_int32, P(sz)]
     L.qtt_matvec_round_graph_create.argtypes = [C.c_int32, P(_MVRCase), C.c_int32, P(vp), P(sz),
-                                                vp, sz, P(vp)]
+                                                vp, sz, C.c_int32, P(vp)]
     L.qtt_matvec_round_graph_launch.argtypes = [vp, vp]
     L.qtt_matvec_round_graph_collect.argtypes = [vp, P(_MVRCase), vp]
     L.qtt_matvec_round_graph_destroy.argtypes = [vp]
@@ -660,12 +660,13 @@ def matvec_round_batched(batch: StepBatch):
 class StepGraph:
     """The batch's hot steps captured into one HIP graph
     (qtt_matvec_round_graph_*): `nbranch` independent branches, branch b
-    running its cases in sequence in the batch's workspace b.  launch()
-    enqueues one replay; collect() waits for it and sets the outputs' ranks
-    and the cases' norm and err.  The graph holds the batch's buffers, so the
-    batch must outlive it."""
+    running its cases in sequence in the batch's workspace b; one graph
+    (per_branch False) or one graph per branch replayed on streams of its
+    own.  launch() enqueues one replay; collect() waits for it and sets the
+    outputs' ranks and the cases' norm and err.  The graph holds the batch's
+    buffers, so the batch must outlive it."""
 
-    def __init__(self, batch: StepBatch, nbranch: int):
+    def __init__(self, batch: StepBatch, nbranch: int, per_branch: bool = False):
         torch = _torch()
         batch.set_workers(nbranch)
         self.batch = batch
@@ -676,7 +677,8 @@ class StepGraph:
         torch.cuda.synchronize()
         _check(lib().qtt_matvec_round_graph_create(batch.n, batch.cases, nbranch, batch.ws_ptr,
                                                    batch.ws_len, _aligned_ptr(self._aux),
-                                                   self._aux.numel() - 256, C.byref(h)))
+                                                   self._aux.numel() - 256, int(per_branch),
+                                                   C.byref(h)))
         self.handle = h
 
     def launch(self, stream=None):

@@ -14,11 +14,26 @@
 
 struct qtt_graph {
   int n = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // one graph (branches as parallel paths) or one graph per branch
+  std::vector<hipGraph_t> graph;
+  std::vector<hipGraphExec_t> exec;
+  // per-branch mode: the streams the branch graphs are replayed on, forked
+  // from and joined back into the caller's stream by events
+  std::vector<hipStream_t> st;
+  std::vector<hipEvent_t> ev;
   std::vector<qtt_tt *> y;  // outputs, for the host ranks at collect
   int32_t *aux_rk = nullptr;
   double *aux_scal = nullptr;
+  ~qtt_graph() {
+    for (auto x : exec)
+      if (x) (void)hipGraphExecDestroy(x);
+    for (auto x : graph)
+      if (x) (void)hipGraphDestroy(x);
+    for (auto x : ev)
+      if (x) (void)hipEventDestroy(x);
+    for (auto x : st)
+      if (x) (void)hipStreamDestroy(x);
+  }
 };
 
 namespace qtt {
@@ -63,14 +78,6 @@ hipError_t launch_step_result(const TTView &t, const double *scal, int32_t *out_
   return hipGetLastError();
 }
 
-struct Streams {
-  std::vector<hipStream_t> s;
-  std::vector<hipEvent_t> e;
-  ~Streams() {
-    for (auto x : e) (void)hipEventDestroy(x);
-    for (auto x : s) (void)hipStreamDestroy(x);
-  }
-};
 
 }  // namespace
 }  // namespace qtt
@@ -89,10 +96,11 @@ qtt_status qtt_matvec_round_graph_aux_bytes(int32_t n, size_t *bytes) {
 qtt_status qtt_matvec_round_graph_create(int32_t n, const qtt_matvec_round_case *cases,
                                          int32_t nbranch, void *const *ws,
                                          const size_t *ws_bytes, void *aux, size_t aux_bytes,
-                                         qtt_graph **out) {
+                                         int32_t per_branch, qtt_graph **out) {
   qtt::clear_stale_error();
   if (!out) return fail(QTT_E_INVAL, "out is NULL");
   *out = nullptr;
+  if (per_branch != 0 && per_branch != 1) return fail(QTT_E_INVAL, "per_branch must be 0 or 1");
   if (n < 1 || !cases) return fail(QTT_E_INVAL, "need n >= 1 cases");
   if (nbranch < 1 || nbranch > 64 || !ws || !ws_bytes)
     return fail(QTT_E_INVAL, "nbranch must be in 1..64 with a workspace each");
@@ -134,81 +142,118 @@ qtt_status qtt_matvec_round_graph_create(int32_t n, const qtt_matvec_round_case 
                                       std::to_string(need[i]) + " bytes for case " +
                                       std::to_string(i));
   }
-  // capture: the origin stream forks to one stream per branch and joins them
-  Streams st;
-  st.s.resize(nbranch + 1, nullptr);
-  st.e.resize(nbranch + 1, nullptr);
-  for (int b = 0; b <= nbranch; ++b) {
-    QTT_HIP(hipStreamCreateWithFlags(&st.s[b], hipStreamNonBlocking));
-    QTT_HIP(hipEventCreateWithFlags(&st.e[b], hipEventDisableTiming));
-  }
-  hipStream_t s0 = st.s[nbranch];
   int32_t *aux_rk = (int32_t *)aux;
   double *aux_scal = (double *)((char *)aux + ((sizeof(int32_t) * kRkStride * n + 255) &
                                                ~size_t(255)));
-  QTT_HIP(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
-  qtt_status cst = QTT_OK;
-  auto capture = [&]() -> qtt_status {
-    QTT_HIP(hipEventRecord(st.e[nbranch], s0));
-    for (int b = 0; b < nbranch; ++b) {
-      hipStream_t sb = st.s[b];
-      QTT_HIP(hipStreamWaitEvent(sb, st.e[nbranch], 0));
-      for (int i : order) {
-        if (branch[i] != b) continue;
-        const qtt_matvec_round_case &c = cases[i];
-        MatvecRoundPlan p;
-        qtt_status r = enqueue_matvec_round(c.A, c.x, c.compute, c.ell, c.seed, c.eps, c.rmax,
-                                            ws[b], ws_bytes[b], sb, p);
-        if (r != QTT_OK) return r;
-        QTT_HIP(launch_pack(p.t.v, (double *)c.y->data, sb));
-        QTT_HIP(launch_step_result(p.t.v, p.w.scal, aux_rk + kRkStride * i, aux_scal + 2 * i,
-                                   c.y->d_ranks, sb));
-      }
-      QTT_HIP(hipEventRecord(st.e[b], sb));
-      QTT_HIP(hipStreamWaitEvent(s0, st.e[b], 0));
+  // the cases of branch b, in order, enqueued on sb
+  auto enqueue_branch = [&](int b, hipStream_t sb) -> qtt_status {
+    for (int i : order) {
+      if (branch[i] != b) continue;
+      const qtt_matvec_round_case &c = cases[i];
+      MatvecRoundPlan p;
+      qtt_status r = enqueue_matvec_round(c.A, c.x, c.compute, c.ell, c.seed, c.eps, c.rmax,
+                                          ws[b], ws_bytes[b], sb, p);
+      if (r != QTT_OK) return r;
+      QTT_HIP(launch_pack(p.t.v, (double *)c.y->data, sb));
+      QTT_HIP(launch_step_result(p.t.v, p.w.scal, aux_rk + kRkStride * i, aux_scal + 2 * i,
+                                 c.y->d_ranks, sb));
     }
     return QTT_OK;
   };
-  cst = capture();
-  hipGraph_t graph = nullptr;
-  hipError_t ec = hipStreamEndCapture(s0, &graph);
-  if (cst != QTT_OK) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return cst;
-  }
-  if (ec != hipSuccess) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return fail(QTT_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
-  }
-  hipGraphExec_t exec = nullptr;
-  ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  if (ec != hipSuccess) {
-    (void)hipGraphDestroy(graph);
-    return fail(QTT_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ec));
-  }
+  // captures what body enqueues on s into an instantiated graph
+  auto capture_into = [&](hipStream_t s, auto body, hipGraph_t &graph,
+                          hipGraphExec_t &exec) -> qtt_status {
+    QTT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const qtt_status cst = body();
+    graph = nullptr;
+    hipError_t ec = hipStreamEndCapture(s, &graph);
+    if (cst != QTT_OK || ec != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      graph = nullptr;
+      if (cst != QTT_OK) return cst;
+      return fail(QTT_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    }
+    ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ec != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      graph = nullptr;
+      return fail(QTT_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ec));
+    }
+    return QTT_OK;
+  };
   qtt_graph *g = new qtt_graph;
   g->n = n;
-  g->graph = graph;
-  g->exec = exec;
   g->aux_rk = aux_rk;
   g->aux_scal = aux_scal;
   g->y.resize(n);
   for (int i = 0; i < n; ++i) g->y[i] = cases[i].y;
+  auto bail = [&](qtt_status st) {
+    delete g;
+    return st;
+  };
+  // one stream and event per branch, and one more for the origin
+  g->st.resize(nbranch + 1, nullptr);
+  g->ev.resize(nbranch + 1, nullptr);
+  for (int b = 0; b <= nbranch; ++b) {
+    if (hipStreamCreateWithFlags(&g->st[b], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&g->ev[b], hipEventDisableTiming) != hipSuccess)
+      return bail(fail(QTT_E_HIP, "stream or event creation failed"));
+  }
+  if (per_branch) {
+    g->graph.resize(nbranch, nullptr);
+    g->exec.resize(nbranch, nullptr);
+    for (int b = 0; b < nbranch; ++b) {
+      qtt_status r = capture_into(g->st[b], [&]() { return enqueue_branch(b, g->st[b]); },
+                                  g->graph[b], g->exec[b]);
+      if (r != QTT_OK) return bail(r);
+    }
+  } else {
+    // the origin stream forks to one stream per branch and joins them
+    hipStream_t s0 = g->st[nbranch];
+    auto body = [&]() -> qtt_status {
+      QTT_HIP(hipEventRecord(g->ev[nbranch], s0));
+      for (int b = 0; b < nbranch; ++b) {
+        QTT_HIP(hipStreamWaitEvent(g->st[b], g->ev[nbranch], 0));
+        qtt_status r = enqueue_branch(b, g->st[b]);
+        if (r != QTT_OK) return r;
+        QTT_HIP(hipEventRecord(g->ev[b], g->st[b]));
+        QTT_HIP(hipStreamWaitEvent(s0, g->ev[b], 0));
+      }
+      return QTT_OK;
+    };
+    g->graph.resize(1, nullptr);
+    g->exec.resize(1, nullptr);
+    qtt_status r = capture_into(s0, body, g->graph[0], g->exec[0]);
+    if (r != QTT_OK) return bail(r);
+  }
   *out = g;
   return QTT_OK;
 }
 
 qtt_status qtt_matvec_round_graph_launch(qtt_graph *g, void *stream) {
   qtt::clear_stale_error();
-  if (!g || !g->exec) return fail(QTT_E_INVAL, "graph is NULL");
-  QTT_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  if (!g || g->exec.empty()) return fail(QTT_E_INVAL, "graph is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if (g->exec.size() == 1) {
+    QTT_HIP(hipGraphLaunch(g->exec[0], s));
+    return QTT_OK;
+  }
+  // per-branch graphs: fork from the caller's stream, replay, join back
+  const int nb = (int)g->exec.size();
+  QTT_HIP(hipEventRecord(g->ev[nb], s));
+  for (int b = 0; b < nb; ++b) {
+    QTT_HIP(hipStreamWaitEvent(g->st[b], g->ev[nb], 0));
+    QTT_HIP(hipGraphLaunch(g->exec[b], g->st[b]));
+    QTT_HIP(hipEventRecord(g->ev[b], g->st[b]));
+    QTT_HIP(hipStreamWaitEvent(s, g->ev[b], 0));
+  }
   return QTT_OK;
 }
 
 qtt_status qtt_matvec_round_graph_collect(qtt_graph *g, qtt_matvec_round_case *cases,
                                           void *stream) {
   qtt::clear_stale_error();
-  if (!g || !g->exec) return fail(QTT_E_INVAL, "graph is NULL");
+  if (!g || g->exec.empty()) return fail(QTT_E_INVAL, "graph is NULL");
   if (!cases) return fail(QTT_E_INVAL, "cases is NULL");
   const int n = g->n;
   std::vector<int32_t> rk(kRkStride * n);
@@ -230,12 +275,7 @@ qtt_status qtt_matvec_round_graph_collect(qtt_graph *g, qtt_matvec_round_case *c
 }
 
 qtt_status qtt_matvec_round_graph_destroy(qtt_graph *g) {
-  if (!g) return QTT_OK;
-  hipError_t e1 = g->exec ? hipGraphExecDestroy(g->exec) : hipSuccess;
-  hipError_t e2 = g->graph ? hipGraphDestroy(g->graph) : hipSuccess;
   delete g;
-  if (e1 != hipSuccess || e2 != hipSuccess)
-    return fail(QTT_E_HIP, "hipGraph destroy failed");
   return QTT_OK;
 }
 

@@ -249,8 +249,8 @@ def test_matvec_round_batched_equals_single(P):
         assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("nbranch", [1, 4])
-def test_matvec_round_graph_equals_single(P, nbranch):
+@pytest.mark.parametrize("nbranch,per_branch", [(1, False), (4, False), (4, True)])
+def test_matvec_round_graph_equals_single(P, nbranch, per_branch):
     """The batch of hot steps captured into one HIP graph (cases on `nbranch`
     branches) gives, on every replay, the ranks, trains, norms and errors of
     the same steps run one at a time (one case with FP32 products).  Between replays the outputs are
@@ -268,7 +268,7 @@ def test_matvec_round_graph_equals_single(P, nbranch):
     ref = [P.matvec_round(K, x, ell, seed, eps, rmax, comp)
            for (K, x, ell, seed, eps, rmax, comp) in items]
     batch = P.StepBatch(items, nbranch)
-    g = P.StepGraph(batch, nbranch)
+    g = P.StepGraph(batch, nbranch, per_branch)
     try:
         for rep in range(3):
             for y in batch.outputs():
