@@ -52,6 +52,9 @@ def _parse():
                     help="skip the level-5 and level-10 solve measurements")
     ap.add_argument("--batch", type=int, default=64,
                     help="cases of the batched-step measurement (0: skip)")
+    ap.add_argument("--batched-steps-only", action="store_true",
+                    help="run only the batched-step measurement and print its JSON (the "
+                         "process the main run starts for it, with 32 hardware queues)")
     ap.add_argument("--batch-solves", type=int, default=256,
                     help="cases of the batched-solve measurement (0: skip)")
     ap.add_argument("--learned", type=int, default=4096,
@@ -533,14 +536,28 @@ def main():
         print("bench.py runs on one GPU only: the multi-GPU form (independent load cases "
               "per GPU) is not built", file=sys.stderr)
         sys.exit(2)
-    # concurrent streams of the batched measurement: one hardware queue each,
-    # up to 32 (HIP's default of 4 per process serialises the workers)
-    try:
-        nq = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
-    except ValueError:
-        nq = 4
-    if nq < 32:
+    if args.batched_steps_only:
+        # concurrent streams of the batched steps: one hardware queue each, up
+        # to 32 (HIP's default of 4 per process serialises the workers)
         os.environ["GPU_MAX_HW_QUEUES"] = "32"
+        import torch
+        import paper_2501_07778_amd as P
+        print(json.dumps(batched_steps(P, torch, args.batch)), flush=True)
+        return
+    # The batched steps run first, in a process of their own with 32 hardware
+    # queues: that many queues slow the single-stream solves of this process
+    # (level-10 ALS about 37 %), so the rest keeps the runtime's default.
+    batched = None
+    if args.batch > 0:
+        import subprocess
+        r = subprocess.run([sys.executable, "-u", os.path.abspath(__file__), "--batched-steps-only",
+                            "--batch", str(args.batch)], stdout=subprocess.PIPE, text=True)
+        if r.returncode != 0:
+            print("batched-step process failed with status %d" % r.returncode, file=sys.stderr)
+            sys.exit(r.returncode if r.returncode > 0 else 1)
+        batched = json.loads(r.stdout.strip().splitlines()[-1])
+        batched["hardware_queues"] = 32
+        note("batched steps done (own process, 32 hardware queues)")
     import torch
     import paper_2501_07778_amd as P
 
@@ -589,7 +606,6 @@ def main():
     note("step: %.3f ms" % (1e3 * dt))
     mixed = mixed_precision(P, torch, K, x, ws, max(2, args.steps // 2))
     note("mixed precision done")
-    batched = batched_steps(P, torch, args.batch) if args.batch > 0 else None
     bsolves = (batched_solves(P, torch, args.batch_solves)
                if (args.batch_solves > 0 and args.solve) else None)
     note("batched measurements done")
