@@ -155,3 +155,48 @@ def test_solve_rejects_malformed_trains_before_any_launch():
     # K whose capacity is below its packed size
     K.capacity = 10
     assert solve(None) == -3 and b"K" in L.qtt_last_error()
+
+
+def test_graph_create_validates_on_the_host():
+    """qtt_matvec_round_graph_create refuses bad arguments, an output whose
+    capacity is below the ranks the rounding may leave, and a branch
+    workspace that is too small, before it creates a stream or captures."""
+    if not os.path.exists(LIB):
+        pytest.skip("libqtt.so not built")
+    import paper_2501_07778_amd as P
+    L = P.lib()
+    T = P._lib._TT
+    D = 3
+    nrow = (C.c_int32 * D)(2, 2, 2)
+    ncol = (C.c_int32 * D)(2, 2, 2)
+    ra = (C.c_int32 * (D + 1))(1, 3, 3, 1)
+    rx = (C.c_int32 * (D + 1))(1, 2, 2, 1)
+    ry = (C.c_int32 * (D + 1))(1, 1, 1, 1)
+    A = T(D, nrow, ncol, ra, 4096, 3 * 4 + 9 * 4 + 3 * 4)
+    x = T(D, nrow, None, rx, 8192, 2 * 2 + 4 * 2 + 2 * 2)
+    y = T(D, nrow, None, ry, 12288, 6 * 2 + 36 * 2 + 6 * 2)   # product ranks 6: enough
+    case = (P._lib._MVRCase * 1)()
+    case[0].A, case[0].x, case[0].y = C.pointer(A), C.pointer(x), C.pointer(y)
+    case[0].compute, case[0].ell, case[0].seed, case[0].eps, case[0].rmax = 0, 0, 1, 1e-8, 0
+    need = C.c_size_t()
+    assert L.qtt_matvec_round_workspace(C.byref(A), C.byref(x), 0, C.byref(need)) == 0
+    ws = (C.c_void_p * 1)(1 << 20)          # never dereferenced: validation fails first
+    wsb = (C.c_size_t * 1)(need.value)
+    aux_n = C.c_size_t()
+    assert L.qtt_matvec_round_graph_aux_bytes(1, C.byref(aux_n)) == 0 and aux_n.value > 0
+    h = C.c_void_p()
+    create = L.qtt_matvec_round_graph_create
+    assert create(0, case, 1, ws, wsb, 1 << 21, aux_n.value, 0, C.byref(h)) == -1
+    assert create(1, case, 0, ws, wsb, 1 << 21, aux_n.value, 0, C.byref(h)) == -1
+    assert create(1, case, 1, ws, wsb, 1 << 21, aux_n.value, 2, C.byref(h)) == -1
+    assert create(1, case, 1, ws, wsb, None, aux_n.value, 0, C.byref(h)) == -3
+    assert create(1, case, 1, ws, wsb, (1 << 21) + 8, aux_n.value, 0, C.byref(h)) == -3
+    y.capacity = 6 * 2 + 36 * 2 + 6 * 2 - 1
+    assert create(1, case, 1, ws, wsb, 1 << 21, aux_n.value, 0, C.byref(h)) == -3
+    assert b"capacity" in L.qtt_last_error()
+    y.capacity += 1
+    wsb[0] = need.value // 2
+    assert create(1, case, 1, ws, wsb, 1 << 21, aux_n.value, 0, C.byref(h)) == -3
+    assert b"branch workspace" in L.qtt_last_error()
+    assert not h.value
+    assert L.qtt_matvec_round_graph_destroy(None) == 0
