@@ -200,11 +200,15 @@ qtt_status qtt_matvec_round_graph_create(int32_t n, const qtt_matvec_round_case 
       return bail(fail(QTT_E_HIP, "stream or event creation failed"));
   }
   if (per_branch) {
-    g->graph.resize(nbranch, nullptr);
-    g->exec.resize(nbranch, nullptr);
+    // graph j holds the j-th branch that has cases (more branches than
+    // cases leave some empty) and is replayed on stream j
     for (int b = 0; b < nbranch; ++b) {
-      qtt_status r = capture_into(g->st[b], [&]() { return enqueue_branch(b, g->st[b]); },
-                                  g->graph[b], g->exec[b]);
+      if (std::find(branch.begin(), branch.end(), b) == branch.end()) continue;
+      const int j = (int)g->exec.size();
+      g->graph.push_back(nullptr);
+      g->exec.push_back(nullptr);
+      qtt_status r = capture_into(g->st[j], [&]() { return enqueue_branch(b, g->st[j]); },
+                                  g->graph[j], g->exec[j]);
       if (r != QTT_OK) return bail(r);
     }
   } else {
@@ -239,13 +243,13 @@ qtt_status qtt_matvec_round_graph_launch(qtt_graph *g, void *stream) {
     return QTT_OK;
   }
   // per-branch graphs: fork from the caller's stream, replay, join back
-  const int nb = (int)g->exec.size();
-  QTT_HIP(hipEventRecord(g->ev[nb], s));
-  for (int b = 0; b < nb; ++b) {
-    QTT_HIP(hipStreamWaitEvent(g->st[b], g->ev[nb], 0));
-    QTT_HIP(hipGraphLaunch(g->exec[b], g->st[b]));
-    QTT_HIP(hipEventRecord(g->ev[b], g->st[b]));
-    QTT_HIP(hipStreamWaitEvent(s, g->ev[b], 0));
+  hipEvent_t fork = g->ev.back();
+  QTT_HIP(hipEventRecord(fork, s));
+  for (size_t j = 0; j < g->exec.size(); ++j) {
+    QTT_HIP(hipStreamWaitEvent(g->st[j], fork, 0));
+    QTT_HIP(hipGraphLaunch(g->exec[j], g->st[j]));
+    QTT_HIP(hipEventRecord(g->ev[j], g->st[j]));
+    QTT_HIP(hipStreamWaitEvent(s, g->ev[j], 0));
   }
   return QTT_OK;
 }

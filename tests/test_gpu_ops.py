@@ -249,10 +249,11 @@ def test_matvec_round_batched_equals_single(P):
         assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("nbranch,per_branch", [(1, False), (4, False), (4, True)])
+@pytest.mark.parametrize("nbranch,per_branch", [(1, False), (4, False), (4, True), (8, True)])
 def test_matvec_round_graph_equals_single(P, nbranch, per_branch):
     """The batch of hot steps captured into one HIP graph (cases on `nbranch`
-    branches) gives, on every replay, the ranks, trains, norms and errors of
+    branches, or one graph per branch; 8 branches for 6 cases leave two
+    empty) gives, on every replay, the ranks, trains, norms and errors of
     the same steps run one at a time (one case with FP32 products).  Between replays the outputs are
     overwritten with NaN and other eager work runs on the same stream, so
     each replay is checked on what it wrote itself."""
