@@ -24,7 +24,8 @@
  *   arrays.  The caller owns every buffer; the library never allocates
  *   device memory: each call takes a caller-provided device workspace
  *   (`ws`, `ws_bytes`, 256-byte aligned) whose size the matching
- *   *_workspace call reports.
+ *   *_workspace call reports.  (The graph form of the batched step holds
+ *   HIP graphs, streams and events of its own, which the runtime owns.)
  * - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
  *   their kernels on it.  A call whose outputs include host-side ranks or
  *   scalars synchronises that stream before returning; this is stated per
