@@ -90,6 +90,29 @@ def step(P, K, x, y, ws, seed, compute="f64"):
     return y
 
 
+def step_as_graph(P, torch, K, x, ws, nsteps: int):
+    """The same step captured once as a HIP graph (qtt_matvec_round_graph_*
+    with one case) and replayed `nsteps` times back to back; its ranks and
+    norm against the eager step with the same seed."""
+    y0, n0, _ = P.matvec_round(K, x, ELL, 0, EPS, RANK, "f64", ws=ws)
+    batch = P.StepBatch([(K, x, ELL, 0, EPS, RANK, "f64")], 1)
+    g = P.StepGraph(batch, 1)
+    try:
+        g.launch()                              # first replay: warm-up
+        g.collect()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            g.launch()
+        g.collect()
+        dt = (time.perf_counter() - t0) / nsteps
+        y = batch.outputs()[0]
+        same = list(y.ranks) == list(y0.ranks) and abs(batch.cases[0].norm - n0) <= 1e-12 * n0
+    finally:
+        g.close()
+    return dict(ms_per_step=round(1e3 * dt, 3), replays=nsteps, equal_to_eager=bool(same))
+
+
 def measured_traffic(summary: str, source: str):
     """HBM bytes per launch of a kernel from its committed counter summary
     in profiles/, or None once any source file the summary lists (the
@@ -604,6 +627,8 @@ def main():
                                ms_per_launch=round(sqr_ms / max(sqr_n, 1), 4),
                                share_of_step=round(sqr_ms / args.steps / (1e3 * dt), 3))
     note("step: %.3f ms" % (1e3 * dt))
+    graph_step = step_as_graph(P, torch, K, x, ws, max(2, args.steps // 2))
+    note("step as a graph: %.3f ms" % graph_step["ms_per_step"])
     mixed = mixed_precision(P, torch, K, x, ws, max(2, args.steps // 2))
     note("mixed precision done")
     bsolves = (batched_solves(P, torch, args.batch_solves)
@@ -636,7 +661,7 @@ def main():
                                % (args.level, 2 * 4 ** args.level, K.D, max(K.ranks), RANK,
                                   EPS, RANK, ELL),
                    "bytes_per_step": nbytes, "result_ranks_max": max(y.ranks),
-                   "mixed_precision": mixed, "batched_steps": batched, "batched_solves": bsolves, "solve_level5": solve5, "solve_level5_fcg": solve5_fcg,
+                   "mixed_precision": mixed, "step_as_graph": graph_step, "batched_steps": batched, "batched_solves": bsolves, "solve_level5": solve5, "solve_level5_fcg": solve5_fcg,
                    "solve_level%d" % args.level: solve10,
                    "solve_level%d_fixed_rank" % args.level: solve10_fixed,
                    "solve_level%d_amen" % args.level: solve10_amen,
