@@ -573,8 +573,13 @@ def main():
     batched = None
     if args.batch > 0:
         import subprocess
-        r = subprocess.run([sys.executable, "-u", os.path.abspath(__file__), "--batched-steps-only",
-                            "--batch", str(args.batch)], stdout=subprocess.PIPE, text=True)
+        try:
+            r = subprocess.run([sys.executable, "-u", os.path.abspath(__file__),
+                                "--batched-steps-only", "--batch", str(args.batch)],
+                               stdout=subprocess.PIPE, text=True, timeout=900)
+        except subprocess.TimeoutExpired:
+            print("batched-step process exceeded 900 s", file=sys.stderr)
+            sys.exit(1)
         if r.returncode != 0:
             print("batched-step process failed with status %d" % r.returncode, file=sys.stderr)
             sys.exit(r.returncode if r.returncode > 0 else 1)
