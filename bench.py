@@ -50,7 +50,7 @@ def _parse():
                          "copy 5 times (for hardware counter passes), print their sizes, exit")
     ap.add_argument("--no-solve", dest="solve", action="store_false",
                     help="skip the level-5 and level-10 solve measurements")
-    ap.add_argument("--batch", type=int, default=64,
+    ap.add_argument("--batch", type=int, default=256,
                     help="cases of the batched-step measurement (0: skip)")
     ap.add_argument("--batched-steps-only", action="store_true",
                     help="run only the batched-step measurement and print its JSON (the "
